@@ -1,0 +1,389 @@
+"""Plain, slow, obviously correct FP64 oracle of the compact 27-point FFT direct solver.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py``; never by the product path.
+
+Paper: Gonzales, Gryazin & Lee, "Scalable Algorithms for High-Order
+Approximations on Three-Dimensional Compact Stencils" (arXiv 1912.03565).
+
+What it computes.  The grid has N_alpha interior points per axis and
+h_alpha = L_alpha/(N_alpha+1) (Section 2).  Row (i, j, l) of the 27-diagonal system
+A U = F holds, for each plane offset o = -1, 0, +1, four weights (a, b, c, d)
+multiplying the corner, x-edge, y-edge and centre points of plane l+o (eq.
+stencil27, Figure 1).  The weights of every scheme are functions of the row l
+only (Sections 3.2 - 3.5).  The solve is Section 3.6: an orthonormal 2-D DST-I
+diagonalises every in-plane 9-point block, leaving N_x N_y independent
+tridiagonal systems along z that are solved by LU without pivoting (Thomas).
+
+Arrays are numpy float64 indexed [z, y, x] (x fastest), matching the paper's row
+index i + N_x j + N_x N_y l.  Interior arrays have shape (nz, ny, nx); closed-grid
+arrays have shape (nz+2, ny+2, nx+2); z-face data are closed planes (ny+2, nx+2).
+
+Readings taken where the paper is silent, garbled or inconsistent (each one is
+listed with its justification in the design notes of the repository):
+  R1  "N^3" counts interior points.
+  R2  the b-term of eq. stencil27 multiplies the two x-neighbours (Figure 1).
+  R3  modal angles theta_n = n pi/(N_x+1), n = 1..N_x (the eigenvector indices).
+  R4  weights depend on the row l; the modal tridiagonal is non-symmetric.
+  R5  non-zero Dirichlet data on the z faces are moved to the right-hand side
+      through the plane-offset weights of rows 1 and N_z.
+  R6-R8 the 6th-order RHS carries -(h^2/20) k_l^2 f + (h^4/60) (k^2)_z f_z (the two
+      terms hidden in the garbled Delta_h(k^2 U)); its "nabla^4 f" is the sum of the
+      three pure fourth derivatives.
+  R10 6th-order derivatives of f by explicit central differences on the closed
+      grid; the fourth differences of the first and last interior layer are the
+      one-sided 6-point formula (2, -9, 16, -14, 6, -1)/h^4.
+  R14 the convection-diffusion d_{l+-1} has an unbalanced parenthesis; read as
+      2/3 - (R_zx+R_zy)/6 +- (h_z gamma/12)(4 - R_zx - R_zy +- h_z gamma).
+  R15 "LU decomposition" of each tridiagonal = Thomas without pivoting.
+"""
+import numpy as np
+
+SCHEMES = ("helm2", "helm4", "helm6", "cd4")
+
+__all__ = [
+    "SCHEMES", "stencil_weights", "rhs", "lift", "sine_matrix", "dst2",
+    "modal_eigenvalues", "thomas", "solve_modal", "solve", "apply_operator",
+    "assemble_dense", "dense_solve", "error_norms", "OracleResult", "closed",
+]
+
+
+# ----------------------------------------------------------------------------
+# Stencil weights, Sections 3.2 - 3.5.
+# W[l-1, o+1] = (a, b, c, d) of row l for plane offset o.
+# ----------------------------------------------------------------------------
+def stencil_weights(scheme, nz, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0):
+    """Weights of every row, shape (nz, 3, 4).
+
+    k2, k2_z, k2_zz are samples of k^2, (k^2)_z, (k^2)_zz at the planes z_0..z_{nz+1}.
+    """
+    W = np.zeros((nz, 3, 4))
+    rzx = hz * hz / (hx * hx)
+    rzy = hz * hz / (hy * hy)
+    ls = np.arange(1, nz + 1)
+    if scheme in ("helm2", "helm4", "helm6"):
+        k2 = np.asarray(k2, dtype=np.float64)
+        km, k0, kp = k2[ls - 1], k2[ls], k2[ls + 1]
+    if scheme == "helm2":
+        # Section 3.2: five non-zero weights.
+        W[:, 0, 3] = 1.0
+        W[:, 2, 3] = 1.0
+        W[:, 1, 1] = rzx
+        W[:, 1, 2] = rzy
+        W[:, 1, 3] = -2.0 * (rzx + rzy + 1.0) + hz * hz * k0
+    elif scheme == "helm4":
+        # Section 3.3.
+        for o, kk in ((0, km), (2, kp)):
+            W[:, o, 1] = (1.0 + rzx) / 12.0
+            W[:, o, 2] = (1.0 + rzy) / 12.0
+            W[:, o, 3] = 2.0 / 3.0 - (rzx + rzy) / 6.0 + hz * hz * kk / 12.0
+        W[:, 1, 0] = (rzx + rzy) / 12.0
+        W[:, 1, 1] = (4.0 * rzx - rzy - 1.0 + hz * hz * k0 / 2.0) / 6.0
+        W[:, 1, 2] = (4.0 * rzy - rzx - 1.0 + hz * hz * k0 / 2.0) / 6.0
+        W[:, 1, 3] = -4.0 * (1.0 + rzx + rzy) / 3.0 + hz * hz * k0 / 2.0
+    elif scheme == "helm6":
+        # Section 3.4 (uniform h).
+        if not (np.isclose(hx, hz, rtol=1e-13, atol=0) and np.isclose(hy, hz, rtol=1e-13, atol=0)):
+            raise ValueError("6th-order scheme needs hx == hy == hz")
+        h = hz
+        kz = np.asarray(k2_z, dtype=np.float64)[ls]
+        kzz = np.asarray(k2_zz, dtype=np.float64)[ls]
+        for o, s, kk in ((0, -1.0, km), (2, 1.0, kp)):
+            W[:, o, 0] = 1.0 / 30.0
+            bc = 1.0 / 10.0 + h ** 2 * kk / 90.0 + s * h ** 3 * kz / 120.0
+            W[:, o, 1] = bc
+            W[:, o, 2] = bc
+            W[:, o, 3] = (7.0 / 15.0 - h ** 2 * kk / 90.0
+                          + s * (h ** 3 * kz / 20.0) * (1.0 / 3.0 + h ** 2 * kk / 6.0))
+        W[:, 1, 0] = 1.0 / 10.0 + h ** 2 * k0 / 90.0
+        W[:, 1, 1] = 7.0 / 15.0 - h ** 2 * k0 / 90.0
+        W[:, 1, 2] = 7.0 / 15.0 - h ** 2 * k0 / 90.0
+        W[:, 1, 3] = (-64.0 / 15.0 + 14.0 * h ** 2 * k0 / 15.0 - h ** 4 * k0 ** 2 / 20.0
+                      + h ** 4 * kzz / 20.0)
+    elif scheme == "cd4":
+        # Section 3.5, with reading R14 of the unbalanced d_{l+-1}.
+        t = hz * gamma
+        for o, s in ((0, -1.0), (2, 1.0)):
+            W[:, o, 1] = (1.0 + rzx) * (2.0 + s * t) / 24.0
+            W[:, o, 2] = (1.0 + rzy) * (2.0 + s * t) / 24.0
+            W[:, o, 3] = 2.0 / 3.0 - (rzx + rzy) / 6.0 + s * (t / 12.0) * (4.0 - rzx - rzy + s * t)
+        W[:, 1, 0] = (rzx + rzy) / 12.0
+        W[:, 1, 1] = (4.0 * rzx - rzy - 1.0) / 6.0
+        W[:, 1, 2] = (4.0 * rzy - rzx - 1.0) / 6.0
+        W[:, 1, 3] = -4.0 * (1.0 + rzx + rzy) / 3.0 - t * t / 6.0
+    else:
+        raise ValueError(f"unknown scheme {scheme}")
+    return W
+
+
+# ----------------------------------------------------------------------------
+# Right-hand sides F (interior), Sections 2.1, 3.2 - 3.5.
+# ----------------------------------------------------------------------------
+def _d2(f, axis):
+    """Second difference f_{-1} - 2 f_0 + f_{+1} on the interior of a closed-grid array."""
+    sl = [slice(1, -1)] * 3
+    lo, mid, hi = list(sl), list(sl), list(sl)
+    lo[axis] = slice(0, -2)
+    hi[axis] = slice(2, None)
+    return f[tuple(lo)] - 2.0 * f[tuple(mid)] + f[tuple(hi)]
+
+
+def _d1(f, axis):
+    """Centred first difference (f_{+1} - f_{-1})/2 on the interior."""
+    sl = [slice(1, -1)] * 3
+    lo, hi = list(sl), list(sl)
+    lo[axis] = slice(0, -2)
+    hi[axis] = slice(2, None)
+    return 0.5 * (f[tuple(hi)] - f[tuple(lo)])
+
+
+def _d4(f, axis):
+    """Fourth difference on the interior (reading R10).
+
+    Central (1, -4, 6, -4, 1) where both neighbours at distance 2 exist; on the
+    first and last interior layer the one-sided (2, -9, 16, -14, 6, -1) formula
+    built from the boundary point and the next five points.
+    """
+    g = np.moveaxis(f, axis, 0)
+    n = g.shape[0] - 2
+    out = np.empty((n,) + g.shape[1:])
+    if n < 4:
+        raise ValueError("the fourth differences need at least 4 interior points per axis")
+    out[1:n - 1] = g[0:n - 2] - 4 * g[1:n - 1] + 6 * g[2:n] - 4 * g[3:n + 1] + g[4:n + 2]
+    out[0] = 2 * g[0] - 9 * g[1] + 16 * g[2] - 14 * g[3] + 6 * g[4] - g[5]
+    out[n - 1] = 2 * g[n + 1] - 9 * g[n] + 16 * g[n - 1] - 14 * g[n - 2] + 6 * g[n - 3] - g[n - 4]
+    out = np.moveaxis(out, 0, axis)
+    # restrict the two transverse axes to the interior
+    sl = [slice(1, -1)] * 3
+    sl[axis] = slice(None)
+    return out[tuple(sl)]
+
+
+def _d2d2(f, a, b):
+    """Product of second differences along axes a and b (a 9-point plane stencil)."""
+    g = np.moveaxis(f, (a, b), (0, 1))
+    s = g[:-2] - 2.0 * g[1:-1] + g[2:]
+    s = s[:, :-2] - 2.0 * s[:, 1:-1] + s[:, 2:]
+    s = np.moveaxis(s, (0, 1), (a, b))
+    sl = [slice(1, -1)] * 3
+    sl[a] = slice(None)
+    sl[b] = slice(None)
+    return s[tuple(sl)]
+
+
+def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0):
+    """F on the interior from f on the closed grid (shape (nz+2, ny+2, nx+2)).
+
+    helm2: F = h_z^2 f (Section 3.2).
+    helm4: F = h_z^2 (1 + sum_alpha h_alpha^2 delta_alpha^2/12) f (eq. scheme4, Section 3.3).
+    cd4:   F = h_z^2 [f + h_x^2/12 f_xx + h_y^2/12 f_yy + h_z^2/12 (gamma f_z + f_zz)] with
+           the derivatives replaced by centred differences (eq. cd_rhs).
+    helm6: F = h^2 [f + h^2/12 sum d2 + h^4/360 sum d4 + h^4/90 sum d2d2
+                    - h^2/20 k_l^2 f + h^4/60 (k^2)_z f_z]   (eq. scheme6, readings R6-R10),
+           where sum_alpha h^2 delta^2 f is corrected by -1/240 h^4 delta^4 so that the h^4
+           coefficient of f_{alpha alpha alpha alpha} is 1/360.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    nz = f.shape[0] - 2
+    inner = f[1:-1, 1:-1, 1:-1]
+    if scheme == "helm2":
+        return hz * hz * inner
+    if scheme == "helm4":
+        return hz * hz * (inner + (_d2(f, 2) + _d2(f, 1) + _d2(f, 0)) / 12.0)
+    if scheme == "cd4":
+        return hz * hz * (inner + _d2(f, 2) / 12.0 + _d2(f, 1) / 12.0
+                          + (hz * gamma * _d1(f, 0) + _d2(f, 0)) / 12.0)
+    if scheme == "helm6":
+        h = hz
+        k0 = np.asarray(k2, dtype=np.float64)[1:nz + 1][:, None, None]
+        kz = np.asarray(k2_z, dtype=np.float64)[1:nz + 1][:, None, None]
+        s2 = _d2(f, 0) + _d2(f, 1) + _d2(f, 2)
+        s4 = _d4(f, 0) + _d4(f, 1) + _d4(f, 2)
+        sx = _d2d2(f, 1, 2) + _d2d2(f, 0, 2) + _d2d2(f, 0, 1)
+        return h * h * (inner + s2 / 12.0 - s4 / 240.0 + sx / 90.0
+                        - h * h * k0 * inner / 20.0 + h ** 3 * kz * _d1(f, 0) / 60.0)
+    raise ValueError(f"unknown scheme {scheme}")
+
+
+# ----------------------------------------------------------------------------
+# In-plane 9-point application and the z-face lift (reading R5).
+# ----------------------------------------------------------------------------
+def _plane9(w, P):
+    """Apply weights w = (a, b, c, d) to the interior of a closed plane P (ny+2, nx+2)."""
+    a, b, c, d = w
+    return (a * (P[:-2, :-2] + P[:-2, 2:] + P[2:, :-2] + P[2:, 2:])
+            + b * (P[1:-1, :-2] + P[1:-1, 2:])
+            + c * (P[:-2, 1:-1] + P[2:, 1:-1])
+            + d * P[1:-1, 1:-1])
+
+
+def lift(W, F, g_lo=None, g_hi=None):
+    """F_1 -= (plane -1 weights of row 1) * g_lo;  F_Nz -= (plane +1 weights of row Nz) * g_hi."""
+    F = np.array(F, dtype=np.float64, copy=True)
+    if g_lo is not None:
+        F[0] -= _plane9(W[0, 0], np.asarray(g_lo, dtype=np.float64))
+    if g_hi is not None:
+        F[-1] -= _plane9(W[-1, 2], np.asarray(g_hi, dtype=np.float64))
+    return F
+
+
+def apply_operator(W, U_closed):
+    """(A U)_{i,j,l} = sum_o sum of the in-plane 9-point weights of plane l+o (eq. stencil27).
+
+    U_closed holds the solution on the closed grid including its boundary values.
+    This is the residual path: it shares nothing with the transform solve.
+    """
+    U = np.asarray(U_closed, dtype=np.float64)
+    nz = U.shape[0] - 2
+    out = np.zeros((nz, U.shape[1] - 2, U.shape[2] - 2))
+    for l in range(1, nz + 1):
+        for o in (-1, 0, 1):
+            out[l - 1] += _plane9(W[l - 1, o + 1], U[l + o])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# The orthonormal sine transform, Section 3.6: V = S_y (x) S_x with
+# S[n-1, i-1] = sqrt(2/(N+1)) sin(pi n i/(N+1)), symmetric and its own inverse.
+# ----------------------------------------------------------------------------
+def sine_matrix(n):
+    k = np.arange(1, n + 1)
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(k, k) / (n + 1))
+
+
+def dst2(F):
+    """Fbar_l = V^T F_l for every plane: sums over x then over y (dense products)."""
+    nz, ny, nx = F.shape
+    Sx, Sy = sine_matrix(nx), sine_matrix(ny)
+    G = np.matmul(F, Sx.T)          # x-sums:  G[l, j, n] = sum_i F[l, j, i] Sx[n, i]
+    return np.matmul(Sy, G)         # y-sums:  Fbar[l, m, n] = sum_j Sy[m, j] G[l, j, n]
+
+
+# ----------------------------------------------------------------------------
+# Modal tridiagonal systems, Section 3.6.
+# ----------------------------------------------------------------------------
+def modal_eigenvalues(W, nx, ny):
+    """lam[l-1, o+1, m-1, n-1] = 4a cos(th_n) cos(ph_m) + 2b cos(th_n) + 2c cos(ph_m) + d."""
+    ct = np.cos(np.pi * np.arange(1, nx + 1) / (nx + 1))[None, :]
+    cp = np.cos(np.pi * np.arange(1, ny + 1) / (ny + 1))[:, None]
+    a, b, c, d = (W[..., q][:, :, None, None] for q in range(4))
+    return 4.0 * a * cp * ct + 2.0 * b * ct + 2.0 * c * cp + d
+
+
+def thomas(lam, Fbar):
+    """Solve lam^-_l W_{l-1} + lam^0_l W_l + lam^+_l W_{l+1} = Fbar_l, W_0 = W_{Nz+1} = 0.
+
+    LU without pivoting (Thomas), every (m, n) column at once.  Returns
+    (W, min |pivot|, number of zero or non-finite pivots).
+    """
+    nz = Fbar.shape[0]
+    cp = np.empty_like(Fbar)
+    dp = np.empty_like(Fbar)
+    minpiv = np.inf
+    bad = 0
+    prev_c = np.zeros_like(Fbar[0])
+    prev_d = np.zeros_like(Fbar[0])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for l in range(nz):
+            piv = lam[l, 1] - lam[l, 0] * prev_c
+            ap = np.abs(piv)
+            ap = ap[np.isfinite(ap)]
+            if ap.size:
+                minpiv = min(minpiv, float(ap.min()))
+            bad += int(np.count_nonzero(~np.isfinite(piv) | (piv == 0)))
+            cp[l] = lam[l, 2] / piv
+            dp[l] = (Fbar[l] - lam[l, 0] * prev_d) / piv
+            prev_c, prev_d = cp[l], dp[l]
+    Wm = np.empty_like(Fbar)
+    Wm[nz - 1] = dp[nz - 1]
+    for l in range(nz - 2, -1, -1):
+        Wm[l] = dp[l] - cp[l] * Wm[l + 1]
+    return Wm, minpiv, bad
+
+
+def solve_modal(W, Fbar):
+    nz, ny, nx = Fbar.shape
+    return thomas(modal_eigenvalues(W, nx, ny), Fbar)
+
+
+class OracleResult:
+    def __init__(self, U, W, F, minpiv, bad):
+        self.U, self.W, self.F, self.minpiv, self.bad = U, W, F, minpiv, bad
+
+
+def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
+          g_lo=None, g_hi=None, W=None, F=None):
+    """U = A^{-1}(F - lift): weights -> F -> lift -> DST -> Thomas -> inverse DST (Section 3.6).
+
+    Either f (closed grid) with a scheme, or an assembled interior F with explicit W.
+    """
+    if W is None:
+        nz = np.asarray(f).shape[0] - 2
+        W = stencil_weights(scheme, nz, hx, hy, hz, k2, k2_z, k2_zz, gamma)
+    if F is None:
+        F = rhs(scheme, f, hx, hy, hz, k2, k2_z, gamma)
+    Fl = lift(W, F, g_lo, g_hi)
+    Fbar = dst2(Fl)
+    What, minpiv, bad = solve_modal(W, Fbar)
+    U = dst2(What)                       # V is its own inverse
+    return OracleResult(U, W, F, minpiv, bad)
+
+
+# ----------------------------------------------------------------------------
+# Brute force for tiny grids: the assembled 27-diagonal matrix (eq. stencil27)
+# and a dense partial-pivot LU solve.
+# ----------------------------------------------------------------------------
+def assemble_dense(W, nx, ny, nz):
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    for l in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = i + nx * (j + ny * l)
+                for o in (-1, 0, 1):
+                    ll = l + o
+                    if not 0 <= ll < nz:
+                        continue
+                    a, b, c, d = W[l, o + 1]
+                    for di in (-1, 0, 1):
+                        for dj in (-1, 0, 1):
+                            ii, jj = i + di, j + dj
+                            if not (0 <= ii < nx and 0 <= jj < ny):
+                                continue
+                            w = (a if (di and dj) else b if di else c if dj else d)
+                            A[r, ii + nx * (jj + ny * ll)] += w
+    return A
+
+
+def dense_solve(W, Fl):
+    nz, ny, nx = Fl.shape
+    A = assemble_dense(W, nx, ny, nz)
+    return np.linalg.solve(A, Fl.reshape(-1)).reshape(nz, ny, nx)
+
+
+# ----------------------------------------------------------------------------
+# Error measures, Section 5.1 (with reading R12 for the two L2 normalisations).
+# ----------------------------------------------------------------------------
+def closed(U, g_lo=None, g_hi=None):
+    nz, ny, nx = U.shape
+    C = np.zeros((nz + 2, ny + 2, nx + 2))
+    C[1:-1, 1:-1, 1:-1] = U
+    if g_lo is not None:
+        C[0] = g_lo
+    if g_hi is not None:
+        C[-1] = g_hi
+    return C
+
+
+def error_norms(U, u_exact_interior, W=None, F=None, g_lo=None, g_hi=None):
+    e = u_exact_interior - U
+    out = {
+        "max_err": float(np.max(np.abs(e))),
+        "l2_err_U": float(np.linalg.norm(e) / np.linalg.norm(U)),
+        "l2_err_u": float(np.linalg.norm(e) / np.linalg.norm(u_exact_interior)),
+    }
+    if W is not None and F is not None:
+        r = F - apply_operator(W, closed(U, g_lo, g_hi))
+        out["l2_res"] = float(np.linalg.norm(r))
+        out["rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(lift(W, F, g_lo, g_hi)))
+    return out
