@@ -247,8 +247,11 @@ def apply_operator(W, U_closed):
 # S[n-1, i-1] = sqrt(2/(N+1)) sin(pi n i/(N+1)), symmetric and its own inverse.
 # ----------------------------------------------------------------------------
 def sine_matrix(n):
+    """The product k*i is reduced modulo 2(N+1) in integers first, so every entry is
+    sin(pi r/(N+1)) with 0 <= r < 2(N+1): no argument rounding for large k*i."""
     k = np.arange(1, n + 1)
-    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(k, k) / (n + 1))
+    r = np.outer(k, k) % (2 * (n + 1))
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * r / (n + 1))
 
 
 def dst2(F):
