@@ -233,9 +233,11 @@ def apply_operator(W, U_closed):
     U_closed holds the solution on the closed grid including its boundary values.
     This is the residual path: it shares nothing with the transform solve.
     """
-    U = np.asarray(U_closed, dtype=np.float64)
+    U = np.asarray(U_closed)
+    if U.dtype != np.longdouble:
+        U = U.astype(np.float64)
     nz = U.shape[0] - 2
-    out = np.zeros((nz, U.shape[1] - 2, U.shape[2] - 2))
+    out = np.zeros((nz, U.shape[1] - 2, U.shape[2] - 2), dtype=np.result_type(U, W))
     for l in range(1, nz + 1):
         for o in (-1, 0, 1):
             out[l - 1] += _plane9(W[l - 1, o + 1], U[l + o])
@@ -246,18 +248,26 @@ def apply_operator(W, U_closed):
 # The orthonormal sine transform, Section 3.6: V = S_y (x) S_x with
 # S[n-1, i-1] = sqrt(2/(N+1)) sin(pi n i/(N+1)), symmetric and its own inverse.
 # ----------------------------------------------------------------------------
-def sine_matrix(n):
+def _pi(dtype):
+    """pi to the working precision (4 atan 1 in that precision)."""
+    return 4 * np.arctan(np.ones((), dtype=dtype))
+
+
+def sine_matrix(n, dtype=np.float64):
     """The product k*i is reduced modulo 2(N+1) in integers first, so every entry is
     sin(pi r/(N+1)) with 0 <= r < 2(N+1): no argument rounding for large k*i."""
     k = np.arange(1, n + 1)
-    r = np.outer(k, k) % (2 * (n + 1))
-    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * r / (n + 1))
+    r = (np.outer(k, k) % (2 * (n + 1))).astype(dtype)
+    two = np.asarray(2, dtype=dtype)
+    return np.sqrt(two / (n + 1)) * np.sin(_pi(dtype) * r / (n + 1))
 
 
-def dst2(F):
+def dst2(F, dtype=None):
     """Fbar_l = V^T F_l for every plane: sums over x then over y (dense products)."""
+    dtype = F.dtype if dtype is None else dtype
+    F = np.asarray(F, dtype=dtype)
     nz, ny, nx = F.shape
-    Sx, Sy = sine_matrix(nx), sine_matrix(ny)
+    Sx, Sy = sine_matrix(nx, dtype), sine_matrix(ny, dtype)
     G = np.matmul(F, Sx.T)          # x-sums:  G[l, j, n] = sum_i F[l, j, i] Sx[n, i]
     return np.matmul(Sy, G)         # y-sums:  Fbar[l, m, n] = sum_j Sy[m, j] G[l, j, n]
 
@@ -265,10 +275,12 @@ def dst2(F):
 # ----------------------------------------------------------------------------
 # Modal tridiagonal systems, Section 3.6.
 # ----------------------------------------------------------------------------
-def modal_eigenvalues(W, nx, ny):
+def modal_eigenvalues(W, nx, ny, dtype=np.float64):
     """lam[l-1, o+1, m-1, n-1] = 4a cos(th_n) cos(ph_m) + 2b cos(th_n) + 2c cos(ph_m) + d."""
-    ct = np.cos(np.pi * np.arange(1, nx + 1) / (nx + 1))[None, :]
-    cp = np.cos(np.pi * np.arange(1, ny + 1) / (ny + 1))[:, None]
+    pi = _pi(dtype)
+    ct = np.cos(pi * np.arange(1, nx + 1, dtype=dtype) / (nx + 1))[None, :]
+    cp = np.cos(pi * np.arange(1, ny + 1, dtype=dtype) / (ny + 1))[:, None]
+    W = np.asarray(W, dtype=dtype)
     a, b, c, d = (W[..., q][:, :, None, None] for q in range(4))
     return 4.0 * a * cp * ct + 2.0 * b * ct + 2.0 * c * cp + d
 
@@ -306,7 +318,7 @@ def thomas(lam, Fbar):
 
 def solve_modal(W, Fbar):
     nz, ny, nx = Fbar.shape
-    return thomas(modal_eigenvalues(W, nx, ny), Fbar)
+    return thomas(modal_eigenvalues(W, nx, ny, Fbar.dtype), Fbar)
 
 
 class OracleResult:
@@ -315,10 +327,15 @@ class OracleResult:
 
 
 def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
-          g_lo=None, g_hi=None, W=None, F=None):
+          g_lo=None, g_hi=None, W=None, F=None, dtype=np.float64):
     """U = A^{-1}(F - lift): weights -> F -> lift -> DST -> Thomas -> inverse DST (Section 3.6).
 
     Either f (closed grid) with a scheme, or an assembled interior F with explicit W.
+    The weights and the right-hand side are formed in FP64 (they define the discrete
+    system); the transforms and the tridiagonal solves run in ``dtype``.  With
+    dtype=np.longdouble (x87 extended, 64-bit significand) the oracle's own rounding
+    stays far below the FP64 level even where small pivots amplify it, so the result is
+    the FP64 system's solution to about 1e-16.  U is returned in FP64.
     """
     if W is None:
         nz = np.asarray(f).shape[0] - 2
@@ -326,9 +343,9 @@ def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
     if F is None:
         F = rhs(scheme, f, hx, hy, hz, k2, k2_z, gamma)
     Fl = lift(W, F, g_lo, g_hi)
-    Fbar = dst2(Fl)
+    Fbar = dst2(Fl, dtype)
     What, minpiv, bad = solve_modal(W, Fbar)
-    U = dst2(What)                       # V is its own inverse
+    U = dst2(What).astype(np.float64)    # V is its own inverse
     return OracleResult(U, W, F, minpiv, bad)
 
 
@@ -369,7 +386,7 @@ def dense_solve(W, Fl):
 # ----------------------------------------------------------------------------
 def closed(U, g_lo=None, g_hi=None):
     nz, ny, nx = U.shape
-    C = np.zeros((nz + 2, ny + 2, nx + 2))
+    C = np.zeros((nz + 2, ny + 2, nx + 2), dtype=U.dtype)
     C[1:-1, 1:-1, 1:-1] = U
     if g_lo is not None:
         C[0] = g_lo

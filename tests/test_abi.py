@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed: nothing here launches a kernel).
+
+* the library loads and exports every entry point declared in include/cs3d.h,
+* argument validation rejects bad descriptions before touching the device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_1912_03565_amd import native
+    return native
+
+
+def test_every_declared_symbol_is_exported(N):
+    with open(os.path.join(ROOT, "include", "cs3d.h")) as fh:
+        hdr = fh.read()
+    declared = set(re.findall(r"\b(cs3d_[a-z_]+)\s*\(", hdr))
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(N.lib, name), name
+    assert set(N.EXPORTS) <= declared
+
+
+def test_status_strings(N):
+    for st in range(8):
+        assert len(N.status_str(st)) > 0
+    assert N.lib.cs3d_version().decode().startswith("cs3d")
+
+
+def _desc(N, **kw):
+    d = N.Desc()
+    d.nx, d.ny, d.nz = kw.get("n", (63, 63, 63))
+    d.hx, d.hy, d.hz = kw.get("h", (1 / 64, 1 / 64, 1 / 64))
+    d.scheme = N.SCHEMES[kw.get("scheme", "helm6")]
+    d.max_rhs = kw.get("max_rhs", 1)
+    d.precision = 0
+    d.refine_steps = kw.get("refine", 0)
+    arr = np.ones(d.nz + 2)
+    keep = [arr]
+    if kw.get("k", True):
+        p = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.k2 = d.k2_z = d.k2_zz = p
+    d._keep = keep
+    return d
+
+
+@pytest.mark.parametrize("case", ["nx0", "nx_big", "h_neg", "h6_unequal", "h6_small", "no_k",
+                                  "bad_scheme", "max_rhs0", "refine_neg", "weights_missing"])
+def test_plan_create_rejects_bad_descriptions(N, case):
+    kw = {}
+    if case == "nx0":
+        kw["n"] = (0, 5, 5)
+    elif case == "nx_big":
+        kw["n"] = (1025, 5, 5)
+    elif case == "h_neg":
+        kw["h"] = (-0.1, 0.1, 0.1)
+    elif case == "h6_unequal":
+        kw["h"] = (0.1, 0.1, 0.2)
+    elif case == "h6_small":
+        kw["n"] = (3, 8, 8)
+    elif case == "no_k":
+        kw["k"] = False
+    elif case == "max_rhs0":
+        kw["max_rhs"] = 0
+    elif case == "refine_neg":
+        kw["refine"] = -1
+    d = _desc(N, **kw)
+    if case == "bad_scheme":
+        d.scheme = 7
+    if case == "weights_missing":
+        d.scheme = N.SCHEMES["weights"]
+    plan = ctypes.c_void_p()
+    st = N.lib.cs3d_plan_create(ctypes.byref(d), None, ctypes.byref(plan))
+    assert st == N.E_INVAL
+    assert not plan.value
+
+
+def test_null_arguments_are_rejected(N):
+    assert N.lib.cs3d_plan_create(None, None, None) == N.E_INVAL
+    assert N.lib.cs3d_solve(None, 1, None, None, None, None, None) == N.E_INVAL
+    assert N.lib.cs3d_solve_assembled(None, 1, None, None, None) == N.E_INVAL
+    assert N.lib.cs3d_set_workspace(None, None, 0) == N.E_INVAL
+    assert N.lib.cs3d_workspace_bytes(None, 1) == 0
+    assert N.lib.cs3d_plan_destroy(None) == N.OK
+    assert N.lib.cs3d_batch_destroy(None) == N.OK
+    assert N.lib.cs3d_get_stats(None, None) == N.E_INVAL

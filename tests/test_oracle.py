@@ -398,3 +398,34 @@ def test_uniform_chunking_is_consistent():
     b = WL.uniform01(77, (400,), offset=600)
     assert np.array_equal(a[600:].numpy(), b.numpy())
     assert float(a.min()) >= 0.0 and float(a.max()) < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Extended-precision mode: same discrete system, residual far below the FP64 level
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,dims", [("helm6", (63, 40, 33)), ("cd4", (20, 17, 9))])
+def test_extended_precision_solve_has_tiny_residual(scheme, dims):
+    nx, ny, nz = dims
+    p = WL.noise_problem(nx, ny, nz, scheme, seed=55)
+    gl, gh = p.g_lo[0].numpy(), p.g_hi[0].numpy()
+    r64 = O.solve(scheme, p.f[0].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz, p.gamma, gl, gh)
+    rld = O.solve(scheme, p.f[0].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz, p.gamma, gl, gh,
+                  dtype=np.longdouble)
+    Fl = O.lift(r64.W, r64.F, gl, gh).astype(np.longdouble)
+    Wld = r64.W.astype(np.longdouble)
+
+    def res(U):
+        # residual of the interior system in extended precision, U given in FP64
+        return float(np.linalg.norm((Fl - O.apply_operator(Wld, O.closed(U.astype(np.longdouble))))
+                                    .astype(np.float64)) / np.linalg.norm(Fl.astype(np.float64)))
+
+    assert res(rld.U) <= res(r64.U) + 1e-16
+    assert res(rld.U) < 5e-16
+    assert np.linalg.norm(rld.U - r64.U) / np.linalg.norm(rld.U) < 1e-10
+    # extended mode matches brute force exactly on a tiny grid
+    q = WL.noise_problem(4, 5, 6, scheme, seed=56)
+    ql, qh = q.g_lo[0].numpy(), q.g_hi[0].numpy()
+    rq = O.solve(scheme, q.f[0].numpy(), q.hx, q.hy, q.hz, q.k2, q.k2_z, q.k2_zz, q.gamma, ql, qh,
+                 dtype=np.longdouble)
+    ref = O.dense_solve(rq.W, O.lift(rq.W, rq.F, ql, qh))
+    assert np.abs(rq.U - ref).max() <= 1e-13 * np.abs(ref).max()
