@@ -1,0 +1,175 @@
+/*
+ * cs3d.h - C ABI of the MI355X direct solver for compact 27-point stencils.
+ *
+ * Method: Gonzales, Gryazin & Lee, "Scalable Algorithms for High-Order
+ * Approximations on Three-Dimensional Compact Stencils" (arXiv 1912.03565).
+ *
+ * The solver computes U = A^{-1}(F - lift) for the 27-diagonal system of
+ * eq. (stencil27) (Section 3.1): the weights (a, b, c, d) of plane offsets
+ * -1, 0, +1 depend on the row's z index only.  Section 3.6 gives the solve:
+ * a 2-D DST-I in x and y diagonalises every 9-point plane block, the modal
+ * eigenvalues lambda = 4a cos(theta_n) cos(phi_m) + 2b cos(theta_n) +
+ * 2c cos(phi_m) + d turn the system into N_x N_y independent tridiagonal
+ * systems along z, each solved by LU without pivoting, and an inverse DST
+ * returns U.
+ *
+ * Problem (Section 1, eq. problem/bc): u_xx + u_yy + u_zz + k(z)^2 u = f, or
+ * the convection-diffusion equation u_xx + u_yy + u_zz + gamma u_z = f
+ * (Section 3.5), on a box with N_alpha interior points and
+ * h_alpha = L_alpha/(N_alpha+1) (Section 2); u = 0 on the x and y faces and
+ * Dirichlet data g on the two z faces.
+ *
+ * Conventions shared by every entry point:
+ *  - Layout: x fastest.  Interior arrays hold nx*ny*nz doubles with point
+ *    (i, j, l) (1-based) at (i-1) + nx*((j-1) + ny*(l-1)), the paper's row order.
+ *    Closed-grid arrays hold (nx+2)*(ny+2)*(nz+2) doubles with point (i, j, l)
+ *    (0-based, boundary included) at i + (nx+2)*(j + (ny+2)*l).  z-face data are
+ *    closed planes of (nx+2)*(ny+2) doubles, ring included.
+ *  - Several right-hand sides are stored back to back (stride = one array).
+ *  - Pointers named dev_* are device (HIP) pointers; everything else is host.
+ *  - The caller owns every data buffer and the workspace; a plan owns only its
+ *    small device tables.  Nothing is allocated during a solve.
+ *  - All solve calls are asynchronous on the given HIP stream (NULL = default
+ *    stream).  cs3d_get_stats synchronises that stream.
+ *  - Errors are returned as cs3d_status codes; nothing aborts or throws.
+ *  - A plan is not thread-safe; distinct plans are.
+ */
+#ifndef CS3D_H
+#define CS3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cs3d_plan_s* cs3d_plan;
+typedef struct cs3d_batch_s* cs3d_batch;
+
+typedef enum {
+  CS3D_OK = 0,
+  CS3D_E_INVAL = 1,          /* bad argument: null pointer, size, spacing, scheme */
+  CS3D_E_NOMEM = 2,          /* a plan table could not be allocated */
+  CS3D_E_DEVICE = 3,         /* a HIP call failed */
+  CS3D_E_SINGULAR = 4,       /* a zero or non-finite pivot was met (from cs3d_get_stats) */
+  CS3D_E_NOTCONVERGED = 5,   /* refinement did not reach its residual target */
+  CS3D_E_UNSUPPORTED = 6,    /* valid request this build cannot serve */
+  CS3D_E_WORKSPACE = 7       /* workspace missing or too small */
+} cs3d_status;
+
+typedef enum {
+  CS3D_HELM2 = 2,     /* 2nd-order 7-point Helmholtz, Section 3.2 (eq. scheme2) */
+  CS3D_HELM4 = 4,     /* 4th-order compact Pade Helmholtz, Sections 2.1 and 3.3 */
+  CS3D_HELM6 = 6,     /* 6th-order compact Helmholtz, Sections 2.1.1 and 3.4 (uniform h) */
+  CS3D_CD4 = 14,      /* 4th-order compact convection-diffusion, Section 3.5 */
+  CS3D_WEIGHTS = 99   /* any stencil of the class eq. stencil27: caller-given weights */
+} cs3d_scheme;
+
+typedef enum {
+  CS3D_FP64 = 0,        /* every stage in FP64 */
+  CS3D_MIXED_FP32 = 1   /* FP32 line transforms and FP32 intermediates, FP64 tridiagonal
+                           solves, FP64 27-point residual and refinement */
+} cs3d_precision;
+
+typedef struct {
+  int nx, ny, nz;          /* interior points per axis (Section 2); >= 1.  The FFT line
+                              transform serves N+1 in {64,...,1024} (powers of two), a
+                              direct sine-sum transform any other N <= 1024.  HELM6 needs
+                              N >= 4 per axis (its fourth differences). */
+  double hx, hy, hz;       /* grid steps > 0.  HELM6 requires hx == hy == hz (Section 2.1.1). */
+  int scheme;              /* cs3d_scheme */
+  const double* k2;        /* host, nz+2 samples of k(z)^2 at z_0..z_{nz+1}; Helmholtz schemes */
+  const double* k2_z;      /* host, nz+2 samples of (k^2)_z; HELM6 only (analytic or O(h^4)) */
+  const double* k2_zz;     /* host, nz+2 samples of (k^2)_zz; HELM6 only */
+  double gamma;            /* convection coefficient; CD4 only */
+  const double* weights;   /* host, nz*3*4 doubles: row l (0..nz-1), plane offset o (-1,0,+1 as
+                              0,1,2), then (a, b, c, d) of eq. stencil27; CS3D_WEIGHTS only */
+  int precision;           /* cs3d_precision */
+  int refine_steps;        /* mixed precision: number of FP64 residual refinement steps (>= 0) */
+  int max_rhs;             /* largest nrhs a solve will be called with (>= 1) */
+} cs3d_desc;
+
+typedef struct {
+  double min_abs_pivot;    /* smallest |pivot| of the tridiagonal LU over the last solve */
+  int64_t bad_pivots;      /* zero or non-finite pivots met in the last solve */
+  int refine_done;         /* refinement steps performed by the last mixed solve */
+  double residual_history[8]; /* FP64 ||F - A U||_2 / ||F||_2 after the initial solve and after
+                                 each refinement step (mixed path; NaN where not computed) */
+  double last_solve_ms;    /* device time of the last solve, from HIP events */
+} cs3d_stats;
+
+/* Build a plan: the stencil weights of every row (Sections 3.2-3.5), modal cosine
+ * tables and transform twiddles, uploaded once to small plan-owned device tables.
+ * desc and the host arrays it points to are only read during this call.
+ * Errors: E_INVAL (bad sizes, spacings, scheme, missing k2/k2_z/k2_zz/weights,
+ * HELM6 with unequal h or N < 4), E_NOMEM, E_DEVICE. */
+cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream, cs3d_plan* out_plan);
+
+/* Free the plan's device tables.  NULL is accepted. */
+cs3d_status cs3d_plan_destroy(cs3d_plan plan);
+
+/* Bytes of device workspace a solve with nrhs right-hand sides needs (0 on error). */
+size_t cs3d_workspace_bytes(cs3d_plan plan, int nrhs);
+
+/* Hand the plan a caller-owned device workspace (256-byte aligned) that stays
+ * valid until the next cs3d_set_workspace or cs3d_plan_destroy.
+ * Errors: E_INVAL (NULL plan or pointer, misaligned). */
+cs3d_status cs3d_set_workspace(cs3d_plan plan, void* dev_workspace, size_t bytes);
+
+/* Solve for nrhs right-hand sides (1 <= nrhs <= max_rhs) from f on the closed grid.
+ * The scheme's RHS operator is applied to f (Sections 3.2-3.5; the 6th-order one as
+ * documented in the design notes), the z-face data are lifted into the first and last
+ * rows through the plane-offset weights, and the solution is written to the interior
+ * array dev_u.  dev_g_lo / dev_g_hi may be NULL (zero data).
+ * Errors: E_INVAL (NULL plan, f or u; nrhs out of range; scheme CS3D_WEIGHTS, which has
+ * no RHS operator - use cs3d_solve_assembled), E_WORKSPACE, E_DEVICE. */
+cs3d_status cs3d_solve(cs3d_plan plan, int nrhs, const double* dev_f, const double* dev_g_lo,
+                       const double* dev_g_hi, double* dev_u, void* hip_stream);
+
+/* Solve A U = F for an interior right-hand side F already assembled by the caller
+ * (any scheme; z-face data, if any, already lifted).  dev_F and dev_u are interior arrays.
+ * Errors: as cs3d_solve. */
+cs3d_status cs3d_solve_assembled(cs3d_plan plan, int nrhs, const double* dev_F, double* dev_u,
+                                 void* hip_stream);
+
+/* FP64 residual of eq. stencil27: dev_r = F - A U over the interior, with F the scheme's
+ * RHS operator applied to dev_f (or dev_F itself when dev_f_is_assembled != 0) and the
+ * z-face data taking the place of the boundary planes of U.
+ * Errors: as cs3d_solve. */
+cs3d_status cs3d_residual(cs3d_plan plan, int nrhs, const double* dev_f, int dev_f_is_assembled,
+                          const double* dev_g_lo, const double* dev_g_hi, const double* dev_u,
+                          double* dev_r, void* hip_stream);
+
+/* Statistics of the last solve on this plan; synchronises the plan's last stream.
+ * Returns E_SINGULAR when the last solve met a zero or non-finite pivot (the stats are
+ * still filled), E_NOTCONVERGED when a mixed solve ended above its residual target. */
+cs3d_status cs3d_get_stats(cs3d_plan plan, cs3d_stats* out_stats);
+
+/* Batches: n independent problems of different sizes, schemes and coefficients solved by
+ * one persistent launch per stage over a device work list, captured once into a HIP graph.
+ * cs3d_batch_create builds one plan per member (desc[i]); the batch owns them.
+ * Each member takes one right-hand side.  The workspace is caller-owned as for plans. */
+cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hip_stream, cs3d_batch* out);
+size_t cs3d_batch_workspace_bytes(cs3d_batch batch);
+cs3d_status cs3d_batch_set_workspace(cs3d_batch batch, void* dev_workspace, size_t bytes);
+/* dev_f[i] / dev_u[i]: device pointers of member i (closed-grid f, interior u).  The
+ * pointer arrays themselves are host arrays.  The first call with a given set of
+ * pointers captures the launches into a HIP graph; later calls with the same pointers
+ * replay it. */
+cs3d_status cs3d_batch_solve(cs3d_batch batch, const double* const* dev_f, double* const* dev_u,
+                             void* hip_stream);
+cs3d_status cs3d_batch_get_stats(cs3d_batch batch, cs3d_stats* out_stats);
+cs3d_status cs3d_batch_destroy(cs3d_batch batch);
+
+/* Static text for a status code. */
+const char* cs3d_status_str(cs3d_status status);
+
+/* Library version string. */
+const char* cs3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CS3D_H */

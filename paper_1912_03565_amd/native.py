@@ -1,0 +1,108 @@
+"""ctypes binding of include/cs3d.h: argument marshalling only.
+
+Every step of the solve runs in libcs3d.so (HIP kernels for gfx950).  PyTorch
+supplies device memory and the HIP stream; it never touches the arithmetic.
+If the library has not been built this module raises on import: there is no
+fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcs3d.so")
+
+OK = 0
+E_INVAL = 1
+E_NOMEM = 2
+E_DEVICE = 3
+E_SINGULAR = 4
+E_NOTCONVERGED = 5
+E_UNSUPPORTED = 6
+E_WORKSPACE = 7
+
+SCHEMES = {"helm2": 2, "helm4": 4, "helm6": 6, "cd4": 14, "weights": 99}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_fp32": 1}
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+        ("scheme", ctypes.c_int),
+        ("k2", ctypes.POINTER(ctypes.c_double)),
+        ("k2_z", ctypes.POINTER(ctypes.c_double)),
+        ("k2_zz", ctypes.POINTER(ctypes.c_double)),
+        ("gamma", ctypes.c_double),
+        ("weights", ctypes.POINTER(ctypes.c_double)),
+        ("precision", ctypes.c_int),
+        ("refine_steps", ctypes.c_int),
+        ("max_rhs", ctypes.c_int),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("min_abs_pivot", ctypes.c_double),
+        ("bad_pivots", ctypes.c_int64),
+        ("refine_done", ctypes.c_int),
+        ("residual_history", ctypes.c_double * 8),
+        ("last_solve_ms", ctypes.c_double),
+    ]
+
+
+EXPORTS = [
+    "cs3d_plan_create", "cs3d_plan_destroy", "cs3d_workspace_bytes", "cs3d_set_workspace",
+    "cs3d_solve", "cs3d_solve_assembled", "cs3d_residual", "cs3d_get_stats",
+    "cs3d_batch_create", "cs3d_batch_workspace_bytes", "cs3d_batch_set_workspace",
+    "cs3d_batch_solve", "cs3d_batch_get_stats", "cs3d_batch_destroy", "cs3d_status_str",
+    "cs3d_version",
+]
+
+
+class CS3DError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed: {msg} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1912_03565_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, sz, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+    sig = {
+        "cs3d_plan_create": (i, [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
+        "cs3d_plan_destroy": (i, [vp]),
+        "cs3d_workspace_bytes": (sz, [vp, i]),
+        "cs3d_set_workspace": (i, [vp, vp, sz]),
+        "cs3d_solve": (i, [vp, i, dp, dp, dp, dp, vp]),
+        "cs3d_solve_assembled": (i, [vp, i, dp, dp, vp]),
+        "cs3d_residual": (i, [vp, i, dp, i, dp, dp, dp, dp, vp]),
+        "cs3d_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
+        "cs3d_batch_create": (i, [i, ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
+        "cs3d_batch_workspace_bytes": (sz, [vp]),
+        "cs3d_batch_set_workspace": (i, [vp, vp, sz]),
+        "cs3d_batch_solve": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
+        "cs3d_batch_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
+        "cs3d_batch_destroy": (i, [vp]),
+        "cs3d_status_str": (ctypes.c_char_p, [i]),
+        "cs3d_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(st):
+    return lib.cs3d_status_str(st).decode()
+
+
+def check(fn, st, allow=()):
+    if st != OK and st not in allow:
+        raise CS3DError(fn, st, status_str(st))
+    return st

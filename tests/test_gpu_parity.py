@@ -1,10 +1,13 @@
-"""GPU parity of the HIP path against the CPU FP64 oracle, through the C ABI.
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
 
 Sizes span several workgroup tiles and ragged tails, both line-transform paths
 (FFT for N+1 a power of two in 64..1024, direct sine sums otherwise), every scheme,
-non-cubic grids, variable k(z) and non-zero z-face data.  The bar for the FP64 path
-is a relative L2 error of 1e-12 against the oracle (both solve the same discrete
-system; their rounding differs by O(kappa eps)).
+non-cubic grids, variable k(z) and non-zero z-face data.  The oracle forms weights
+and right-hand side in FP64 and solves that discrete system with extended-precision
+transforms and Thomas sweeps, so its own rounding is far below the FP64 level; the
+bar for the FP64 GPU path is a relative L2 error of 1e-12, or four times the error of
+the plain FP64 oracle on the same system where small pivots of the LU without
+pivoting (Section 3.6) push that FP64 floor above 1e-12.
 """
 import numpy as np
 import pytest
@@ -35,6 +38,16 @@ def _oracle(p, r=0, F=None, W=None):
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _bar(p, ref, r=0):
+    """Parity bar: 1e-12, or 4x the error that the plain FP64 oracle itself makes on this
+    discrete system when that is larger (ill-conditioned modal systems)."""
+    gl = None if p.g_lo is None else p.g_lo[r].numpy()
+    gh = None if p.g_hi is None else p.g_hi[r].numpy()
+    u64 = O.solve(p.scheme, p.f[r].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz, p.gamma,
+                  gl, gh).U
+    return max(TOL_FP64, 4.0 * _rel(u64, ref.U))
 
 
 def _gpu_solve(cs3d, p):
@@ -73,8 +86,10 @@ def test_solve_matches_oracle(cs3d, scheme, nx, ny, nz):
     u, st = _gpu_solve(cs3d, p)
     ref = _oracle(p)
     err = _rel(u[0], ref.U)
-    print(f"  rel err {err:.3e}  minpiv gpu {st['min_abs_pivot']:.3e} oracle {ref.minpiv:.3e}", flush=True)
-    assert err < TOL_FP64, err
+    bar = _bar(p, ref)
+    print(f"  rel err {err:.3e} (bar {bar:.1e})  minpiv gpu {st['min_abs_pivot']:.3e} "
+          f"oracle {ref.minpiv:.3e}", flush=True)
+    assert err < bar, err
     assert st["bad_pivots"] == 0
     assert abs(st["min_abs_pivot"] - ref.minpiv) <= 1e-9 * max(1.0, ref.minpiv)
 
@@ -84,7 +99,7 @@ def test_multiple_rhs_share_one_plan(cs3d):
     u, _ = _gpu_solve(cs3d, p)
     for r in range(3):
         ref = _oracle(p, r)
-        assert _rel(u[r], ref.U) < TOL_FP64
+        assert _rel(u[r], ref.U) < _bar(p, ref, r)
 
 
 def test_solve_assembled_with_generic_weights(cs3d):
