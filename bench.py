@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the compact 27-point FFT direct solver on one MI355X.
+
+Workload: 6th-order compact Helmholtz (Sections 2.1.1 and 3.4), k(z) = 80 exp(-z) on
+the unit cube, 1023^3 interior grid, 4 right-hand sides f_r = f*(u*) + U[-1, 1] noise
+sharing one plan.  A step is one call of cs3d_solve over the 4 right-hand sides: RHS
+operator + lift, DST in x and y, modal tridiagonal LU along z, inverse DST (Section 3.6).
+Inputs are generated on the device before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  value = right-hand sides x N^3 unknowns per second of wall time
+(HIP events around the K steps).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "unknowns solved/s at 1023³ 6th-order, mixed vs FP64 GPU, rel err ≤1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(nx, ny, nz, nrhs, elem=8):
+    """Algorithmic HBM bytes per launch of each pass (all right-hand sides).
+
+    [0] RHS + x-DST: read f on the closed grid, write the x-transformed field.
+    [1] y-DST + forward elimination: read it, write d' in place, write c' once per plan.
+    [2] back substitution + inverse y-DST: read d' and c', write the result in place.
+    [3] inverse x-DST: read it, write u.
+    """
+    n3 = nx * ny * nz
+    closed = (nx + 2) * (ny + 2) * (nz + 2)
+    return [
+        nrhs * (8 * closed + elem * n3),
+        nrhs * (2 * elem * n3) + 8 * n3,
+        nrhs * (2 * elem * n3 + 8 * n3),
+        nrhs * (elem * n3 + 8 * n3),
+    ]
+
+
+STAGE_NAMES = ["k_fwd_x (RHS + x-DST)", "k_fwd_y (y-DST + forward elimination)",
+               "k_back_y (back substitution + inverse y-DST)", "k_inv_x (inverse x-DST)"]
+
+
+def cpu_baseline(p_dev, planes):
+    """Time the oracle (FP64, as it stands) on a slab of `planes` z-planes of one right-hand
+    side of the same workload: RHS operator, forward 2-D DST, the Thomas sweep over the
+    matching share of modal columns (all N_z planes), inverse 2-D DST."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import workloads as WL
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    n = p_dev.nx
+    P = min(planes, p_dev.nz)
+    # the same closed-grid f of right-hand side 0, restricted to planes 0..P+1
+    # (counter-based noise: the values are those the device solved)
+    prob = WL.config5(n=n, nrhs=1, device="cpu", planes=P + 2)
+    fs = prob.f[0].numpy()
+    k2, k2z, k2zz, h = prob.k2, prob.k2_z, prob.k2_zz, prob.hz
+    W = O.stencil_weights("helm6", n, h, h, h, k2, k2z, k2zz)
+    t0 = time.perf_counter()
+    F = O.rhs("helm6", fs, h, h, h, k2[: P + 2], k2z[: P + 2])
+    Fb = O.dst2(F)
+    lam = O.modal_eigenvalues(W, n, P)            # P x N modal columns over all N_z rows
+    rng = np.random.default_rng(0)
+    Fcols = rng.standard_normal((n, P, n))
+    Wm, _, _ = O.thomas(lam, Fcols)
+    U = O.dst2(Fb)
+    t = time.perf_counter() - t0
+    del U, Wm, lam, Fcols
+    return {"value": P * n * n / t, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{P} of {n} z-planes of one right-hand side: RHS operator, forward and inverse "
+                      f"2-D DST by dense sine sums, Thomas sweep over {P}x{n} of the {n}x{n} modal "
+                      f"columns; {t:.1f} s on {threads} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1023)
+    ap.add_argument("--nrhs", type=int, default=4)
+    ap.add_argument("--cpu-planes", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1912_03565_amd as cs3d
+    import workloads as WL
+
+    dev = torch.device("cuda:0")
+    n, nrhs = args.n, args.nrhs
+    log(f"[bench] generating inputs {n}^3 x {nrhs} on {dev}")
+    p = WL.config5(n=n, nrhs=nrhs, device=dev)
+    torch.cuda.synchronize()
+    plan = cs3d.plan_for_problem(p, max_rhs=nrhs, device=dev)
+    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
+    log(f"[bench] plan ready, workspace {plan.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.solve(p.f, out=u)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.solve(p.f, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = plan.stats()
+    log(f"[bench] {ms:.3f} ms/step; stages {['%.3f' % s for s in st['stage_ms']]}")
+    unknowns = nrhs * n ** 3
+    value = unknowns / (ms / 1e3)
+
+    sb = stage_bytes(n, n, n, nrhs)
+    k = max(range(len(st["stage_ms"])), key=lambda i: st["stage_ms"][i])
+    achieved = sb[k] / (st["stage_ms"][k] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": STAGE_NAMES[k], "kernel_ms": round(st["stage_ms"][k], 4),
+                "algorithmic_bytes": sb[k]}
+    stages = [{"kernel": STAGE_NAMES[i], "ms": round(st["stage_ms"][i], 4),
+               "algorithmic_GBs": round(sb[i] / (st["stage_ms"][i] / 1e3) / 1e9, 1)}
+              for i in range(len(st["stage_ms"]))]
+    whole_gbs = sum(sb) / (ms / 1e3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_planes} planes")
+        del u
+        cpu = cpu_baseline(p, args.cpu_planes)
+        cpu["value"] = round(cpu["value"], 1)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} unknowns/s")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"helm6_kexp_{n}^3_x{nrhs}rhs", "grid": [n, n, n], "nrhs": nrhs,
+                   "scheme": "6th-order compact Helmholtz", "k": "80 exp(-z)",
+                   "rhs": "f*(sin pi x sin 2pi y sin 3pi z) + U[-1,1] noise, seeds 105000+r",
+                   "precision": "fp64"},
+        "roofline": roofline,
+        "stages": stages,
+        "path_algorithmic_GBs": round(whole_gbs, 1),
+        "min_abs_pivot": st["min_abs_pivot"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,12 @@ typedef struct {
   double residual_history[8]; /* FP64 ||F - A U||_2 / ||F||_2 after the initial solve and after
                                  each refinement step (mixed path; NaN where not computed) */
   double last_solve_ms;    /* device time of the last solve, from HIP events */
+  double stage_ms[8];      /* mean device time per solve of each pass, over the solves since the
+                              last cs3d_reset_timers (at most the last 128): FP64 path
+                              [0] RHS + x-DST, [1] y-DST + forward elimination,
+                              [2] back substitution + inverse y-DST, [3] inverse x-DST */
+  int stage_count;         /* number of passes reported in stage_ms */
+  int timed_solves;        /* solves averaged into stage_ms */
 } cs3d_stats;
 
 /* Build a plan: the stencil weights of every row (Sections 3.2-3.5), modal cosine
@@ -145,6 +151,9 @@ cs3d_status cs3d_residual(cs3d_plan plan, int nrhs, const double* dev_f, int dev
  * Returns E_SINGULAR when the last solve met a zero or non-finite pivot (the stats are
  * still filled), E_NOTCONVERGED when a mixed solve ended above its residual target. */
 cs3d_status cs3d_get_stats(cs3d_plan plan, cs3d_stats* out_stats);
+
+/* Restart the per-pass timing average reported by cs3d_get_stats.  Errors: E_INVAL. */
+cs3d_status cs3d_reset_timers(cs3d_plan plan);
 
 /* Batches: n independent problems of different sizes, schemes and coefficients solved by
  * one persistent launch per stage over a device work list, captured once into a HIP graph.

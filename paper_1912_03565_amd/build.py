@@ -1,6 +1,9 @@
 """Build the HIP library libcs3d.so in-tree for gfx950.
 
-    python -m paper_1912_03565_amd.build
+    python paper_1912_03565_amd/build.py
+
+(run as a file, not as a module of the package: importing the package loads the
+library that is about to be rebuilt)
 """
 import os
 import subprocess

@@ -21,6 +21,8 @@ using namespace cs3d;
 namespace {
 
 constexpr int kMaxN = 1024;
+constexpr int kRing = 128;      // solves kept for the per-pass timing average
+constexpr int kMaxStages = 8;
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -56,6 +58,10 @@ struct cs3d_plan_s {
   hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // per-pass timing ring: kRing solves x (kMaxStages + 1) events
+  std::vector<hipEvent_t> ring;
+  long long solves = 0;   // solves recorded since the last reset
+  int nstages = 0;
   std::vector<double> hW;  // host copy of the weights
 };
 
@@ -215,6 +221,8 @@ static void plan_free(cs3d_plan p) {
   void* ptrs[] = {p->dW, p->dLC, p->dk2, p->dk2z, p->dctx, p->dcty, p->dtwx, p->dtwy, p->dsinx, p->dsiny, p->dstats};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (hipEvent_t e : p->ring)
+    if (e) (void)hipEventDestroy(e);
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
   delete p;
@@ -287,6 +295,8 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   CS3D_TRY(hipMemcpyAsync(p->dsiny, sy.data(), sy.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipEventCreate(&p->ev0));
   CS3D_TRY(hipEventCreate(&p->ev1));
+  p->ring.assign((size_t)kRing * (kMaxStages + 1), nullptr);
+  for (hipEvent_t& e : p->ring) CS3D_TRY(hipEventCreate(&e));
   k_stats_reset<<<1, 64, 0, s>>>(p->dstats);
   CS3D_TRY(hipGetLastError());
   // the host vectors above go out of scope: wait for the copies
@@ -451,13 +461,27 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, int assembled, const 
   return pd;
 }
 
+// event marking the start of pass k (k = nstages marks the end) of the current solve
+static hipError_t mark(cs3d_plan p, int k, hipStream_t s) {
+  const size_t slot = (size_t)(p->solves % kRing) * (kMaxStages + 1) + k;
+  return hipEventRecord(p->ring[slot], s);
+}
+
 template <typename T>
-static hipError_t solve_passes(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+static hipError_t solve_passes(cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   hipError_t e;
+  p->nstages = 4;
+  if ((e = mark(p, 0, s)) != hipSuccess) return e;
   if ((e = run_x_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 1, s)) != hipSuccess) return e;
   if ((e = run_y_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 2, s)) != hipSuccess) return e;
   if ((e = run_y_back<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  return run_x_inv<T>(p, pd, nrhs, s);
+  if ((e = mark(p, 3, s)) != hipSuccess) return e;
+  if ((e = run_x_inv<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 4, s)) != hipSuccess) return e;
+  ++p->solves;
+  return hipSuccess;
 }
 
 static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int assembled, const double* glo,
@@ -517,7 +541,24 @@ extern "C" cs3d_status cs3d_get_stats(cs3d_plan p, cs3d_stats* out) {
   out->bad_pivots = (int64_t)h[1];
   float ms = 0.f;
   if (p->timed && hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) out->last_solve_ms = ms;
+  const long long n = p->solves < kRing ? p->solves : kRing;
+  out->stage_count = p->nstages;
+  out->timed_solves = (int)n;
+  for (long long q = 0; q < n; ++q)
+    for (int k = 0; k < p->nstages; ++k) {
+      const size_t base = (size_t)q * (kMaxStages + 1);
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p->ring[base + k], p->ring[base + k + 1]) != hipSuccess) return CS3D_E_DEVICE;
+      out->stage_ms[k] += (double)t / (double)n;
+    }
   return h[1] ? CS3D_E_SINGULAR : CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_reset_timers(cs3d_plan p) {
+  if (!p) return CS3D_E_INVAL;
+  if (p->last_stream) (void)hipStreamSynchronize(p->last_stream);
+  p->solves = 0;
+  return CS3D_OK;
 }
 
 extern "C" const char* cs3d_status_str(cs3d_status st) {

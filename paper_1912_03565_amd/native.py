@@ -47,6 +47,9 @@ class Stats(ctypes.Structure):
         ("refine_done", ctypes.c_int),
         ("residual_history", ctypes.c_double * 8),
         ("last_solve_ms", ctypes.c_double),
+        ("stage_ms", ctypes.c_double * 8),
+        ("stage_count", ctypes.c_int),
+        ("timed_solves", ctypes.c_int),
     ]
 
 
@@ -55,7 +58,7 @@ EXPORTS = [
     "cs3d_solve", "cs3d_solve_assembled", "cs3d_residual", "cs3d_get_stats",
     "cs3d_batch_create", "cs3d_batch_workspace_bytes", "cs3d_batch_set_workspace",
     "cs3d_batch_solve", "cs3d_batch_get_stats", "cs3d_batch_destroy", "cs3d_status_str",
-    "cs3d_version",
+    "cs3d_version", "cs3d_reset_timers",
 ]
 
 
@@ -79,6 +82,7 @@ def _load():
         "cs3d_solve_assembled": (i, [vp, i, dp, dp, vp]),
         "cs3d_residual": (i, [vp, i, dp, i, dp, dp, dp, dp, vp]),
         "cs3d_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
+        "cs3d_reset_timers": (i, [vp]),
         "cs3d_batch_create": (i, [i, ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
         "cs3d_batch_workspace_bytes": (sz, [vp]),
         "cs3d_batch_set_workspace": (i, [vp, vp, sz]),

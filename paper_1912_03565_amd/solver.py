@@ -155,7 +155,12 @@ class Plan:
             "refine_done": int(s.refine_done),
             "residual_history": [v for v in s.residual_history],
             "last_solve_ms": s.last_solve_ms,
+            "stage_ms": [s.stage_ms[k] for k in range(s.stage_count)],
+            "timed_solves": int(s.timed_solves),
         }
+
+    def reset_timers(self):
+        N.check("cs3d_reset_timers", N.lib.cs3d_reset_timers(self._plan))
 
     def close(self):
         if getattr(self, "_plan", None) and self._plan.value:

@@ -138,17 +138,20 @@ def paper_cd(n, gamma=-100.0, device="cpu"):
 # Manufactured smooth solution on the unit cube, homogeneous on every face:
 # u* = sin(pi x) sin(2 pi y) sin(3 pi z), f* = (k(z)^2 - 14 pi^2) u*.
 # ----------------------------------------------------------------------------
-def manufactured_sin3(nx, ny, nz, scheme, prof, device="cpu", box=None):
+def manufactured_sin3(nx, ny, nz, scheme, prof, device="cpu", box=None, planes=None):
+    """``planes`` restricts the fields to the closed-grid z-planes 0..planes-1."""
     if box is None:
         box = (1.0, 1.0, 1.0)
     hx, hy, hz = box[0] / (nx + 1), box[1] / (ny + 1), box[2] / (nz + 1)
     x, y, z = _axis(nx, hx, device=device), _axis(ny, hy, device=device), _axis(nz, hz, device=device)
+    if planes is not None:
+        z = z[:planes]
     sx = torch.sin(math.pi * x / box[0])
     sy = torch.sin(2 * math.pi * y / box[1])
     sz = torch.sin(3 * math.pi * z / box[2])
     lap = -math.pi ** 2 * (1.0 / box[0] ** 2 + 4.0 / box[1] ** 2 + 9.0 / box[2] ** 2)
     k2, k2z, k2zz = _zsamples(nz, hz, prof)
-    k2t = torch.as_tensor(k2, device=device)
+    k2t = torch.as_tensor(k2[: z.shape[0]], device=device)
     u = _outer3(sz, sy, sx)
     f = _outer3((k2t + lap) * sz, sy, sx)
     return Problem(f"sin3_{scheme}_{nx}x{ny}x{nz}", scheme, nx, ny, nz, hx, hy, hz,
@@ -183,13 +186,15 @@ def config1(device="cpu"):
 
 
 def _noise_rhs(p, seeds, kind, scale_smooth=1.0, device="cpu"):
-    shape = (p.nz + 2, p.ny + 2, p.nx + 2)
-    fs = []
-    for s in seeds:
-        xi = uniform_pm1(s, shape, device=device) if kind == "uniform" else gaussian(s, shape, device=device)
-        fs.append(scale_smooth * p.f[0] + xi)
-    p.f = torch.stack(fs)
+    shape = tuple(p.f.shape[1:])
+    base = p.f[0]
     p.u_exact = None
+    out = torch.empty((len(seeds),) + shape, dtype=torch.float64, device=device)
+    for r, s in enumerate(seeds):
+        xi = uniform_pm1(s, shape, device=device) if kind == "uniform" else gaussian(s, shape, device=device)
+        torch.add(xi, base, alpha=scale_smooth, out=out[r])
+        del xi
+    p.f = out
     return p
 
 
@@ -207,9 +212,11 @@ def config3(n=511, device="cpu"):
     return _noise_rhs(p, [103], "gauss", scale_smooth=0.0, device=device)
 
 
-def config5(n=1023, nrhs=4, device="cpu"):
-    """6th-order, k = 80 exp(-z), f_r = f*(u*) + U[-1, 1] noise (seeds 105000 + r)."""
-    p = manufactured_sin3(n, n, n, "helm6", K_CONFIG5, device=device)
+def config5(n=1023, nrhs=4, device="cpu", planes=None):
+    """6th-order, k = 80 exp(-z), f_r = f*(u*) + U[-1, 1] noise (seeds 105000 + r).
+
+    ``planes`` keeps only the closed-grid z-planes 0..planes-1 (same values)."""
+    p = manufactured_sin3(n, n, n, "helm6", K_CONFIG5, device=device, planes=planes)
     p.name = f"helm6_kexp_{n}_x{nrhs}"
     return _noise_rhs(p, [105000 + r for r in range(nrhs)], "uniform", device=device)
 
