@@ -33,22 +33,24 @@ def log(*a):
 def stage_bytes(nx, ny, nz, nrhs, elem=8):
     """Algorithmic HBM bytes per launch of each pass (all right-hand sides).
 
-    [0] RHS + x-DST: read f on the closed grid, write the x-transformed field.
-    [1] y-DST + forward elimination: read it, write d' in place, write c' once per plan.
-    [2] back substitution + inverse y-DST: read d' and c', write the result in place.
-    [3] inverse x-DST: read it, write u.
+    [0] RHS operator: read f on the closed grid, write the interior F.
+    [1] x-DST: read F, write the x-transformed field.
+    [2] y-DST + forward elimination: read it, write d' in place, write c' once per plan.
+    [3] back substitution + inverse y-DST: read d' and c', write the result in place.
+    [4] inverse x-DST: read it, write u.
     """
     n3 = nx * ny * nz
     closed = (nx + 2) * (ny + 2) * (nz + 2)
     return [
-        nrhs * (8 * closed + elem * n3),
+        nrhs * (8 * closed + 8 * n3),
+        nrhs * (8 * n3 + elem * n3),
         nrhs * (2 * elem * n3) + 8 * n3,
         nrhs * (2 * elem * n3 + 8 * n3),
         nrhs * (elem * n3 + 8 * n3),
     ]
 
 
-STAGE_NAMES = ["k_fwd_x (RHS + x-DST)", "k_fwd_y (y-DST + forward elimination)",
+STAGE_NAMES = ["k_rhs (RHS operator + lift)", "k_fwd_x (x-DST)", "k_fwd_y (y-DST + forward elimination)",
                "k_back_y (back substitution + inverse y-DST)", "k_inv_x (inverse x-DST)"]
 
 
@@ -100,6 +102,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--cpu-planes", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="after the timed steps, copy 2 GiB once with a plain device copy "
+                         "(the reference for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -147,6 +152,15 @@ def main():
                "algorithmic_GBs": round(sb[i] / (st["stage_ms"][i] / 1e3) / 1e9, 1)}
               for i in range(len(st["stage_ms"]))]
     whole_gbs = sum(sb) / (ms / 1e3) / 1e9
+
+    if args.traffic_probe:
+        src = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] traffic probe: copied 2 GiB")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

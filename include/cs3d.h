@@ -99,8 +99,8 @@ typedef struct {
   double last_solve_ms;    /* device time of the last solve, from HIP events */
   double stage_ms[8];      /* mean device time per solve of each pass, over the solves since the
                               last cs3d_reset_timers (at most the last 128): FP64 path
-                              [0] RHS + x-DST, [1] y-DST + forward elimination,
-                              [2] back substitution + inverse y-DST, [3] inverse x-DST */
+                              [0] RHS operator, [1] x-DST, [2] y-DST + forward elimination,
+                              [3] back substitution + inverse y-DST, [4] inverse x-DST */
   int stage_count;         /* number of passes reported in stage_ms */
   int timed_solves;        /* solves averaged into stage_ms */
 } cs3d_stats;

@@ -20,7 +20,7 @@ using namespace cs3d;
 
 namespace {
 
-constexpr int kMaxN = 1024;
+constexpr int kMaxN = 1023;
 constexpr int kRing = 128;      // solves kept for the per-pass timing average
 constexpr int kMaxStages = 8;
 
@@ -337,89 +337,118 @@ extern "C" cs3d_status cs3d_set_workspace(cs3d_plan p, void* dev, size_t bytes) 
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
-template <typename T>
-static size_t lds_bytes_x(const cs3d_plan p) {
-  const int reg = p->fx ? region_elems<T, 64>(0) * (p->fx / 64) : region_elems<T, 0>(p->d.nx);
-  const size_t a = (size_t)kTileJ * reg * sizeof(T);
-  const size_t b = (size_t)kTileJ * p->d.nx * sizeof(T);
-  return a > b ? a : b;
+template <typename T, int MX>
+static size_t lds_bytes_x_t(const cs3d_plan p) {
+  const size_t a = (size_t)kTileJ * line_buf_elems<T, MX>(p->d.nx) * sizeof(T);
+  const size_t b = (size_t)kTileJ * tile_stride(p->d.nx) * sizeof(T);
+  return (a > b ? a : b) + tw_bytes<T, MX>();
 }
 
-template <typename T>
-static size_t lds_bytes_y(const cs3d_plan p) {
-  const int reg = p->fy ? region_elems<T, 64>(0) * (p->fy / 64) : region_elems<T, 0>(p->d.ny);
-  return (size_t)kWavesY * reg * sizeof(T);
+template <typename T, int MY>
+static size_t lds_bytes_y_t(const cs3d_plan p) {
+  return (size_t)YCfg<MY>::LPB * line_buf_elems<T, MY>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
 }
 
-template <typename KernelT>
-static hipError_t launch(KernelT kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const ProbDev& pd) {
+template <typename KernelT, typename... Args>
+static hipError_t launch(KernelT kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, grid, block, lds, s, pd);
+  hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
   return hipGetLastError();
 }
 
+// persistent x-pass grid: as many workgroups as fit on the device at once
+template <typename KernelT>
+static int resident_blocks(KernelT kern, int threads, size_t lds, int ntiles) {
+  int dev = 0, per_cu = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), threads, lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const long long b = (long long)per_cu * cus;
+  return (int)(b < ntiles ? b : ntiles);
+}
+
+template <typename T, int MX>
+static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
+  const size_t lds = lds_bytes_x_t<T, MX>(p);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int nb = resident_blocks(k_fwd_x<T, MX>, 64 * kTileJ, lds, ntiles);
+  return launch(k_fwd_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+}
+
+template <typename T, int MX>
+static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
+  const size_t lds = lds_bytes_x_t<T, MX>(p);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int nb = resident_blocks(k_inv_x<T, MX>, 64 * kTileJ, lds, ntiles);
+  return launch(k_inv_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+}
+
+template <typename T, int MY>
+static hipError_t run_y_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  dim3 grid((p->d.nx + YCfg<MY>::LPB - 1) / YCfg<MY>::LPB, nrhs), block(kBlockY);
+  return launch(k_fwd_y<T, MY>, grid, block, lds_bytes_y_t<T, MY>(p), s, pd);
+}
+
+template <typename T, int MY>
+static hipError_t run_y_back_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  dim3 grid((p->d.nx + YCfg<MY>::LPB - 1) / YCfg<MY>::LPB, nrhs), block(kBlockY);
+  return launch(k_back_y<T, MY>, grid, block, lds_bytes_y_t<T, MY>(p), s, pd);
+}
+
+#define CS3D_DISPATCH(fn, M, ...)                 \
+  switch (M) {                                    \
+    case 64: return fn<T, 64>(__VA_ARGS__);       \
+    case 128: return fn<T, 128>(__VA_ARGS__);     \
+    case 256: return fn<T, 256>(__VA_ARGS__);     \
+    case 512: return fn<T, 512>(__VA_ARGS__);     \
+    case 1024: return fn<T, 1024>(__VA_ARGS__);   \
+    default: return fn<T, 0>(__VA_ARGS__);        \
+  }
+
 template <typename T>
 static hipError_t run_x_fwd(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid(p->ldy / kTileJ, p->d.nz, nrhs), block(1024);
-  const size_t lds = lds_bytes_x<T>(p);
-  switch (p->fx) {
-    case 64: return launch(k_fwd_x<T, 64>, grid, block, lds, s, pd);
-    case 128: return launch(k_fwd_x<T, 128>, grid, block, lds, s, pd);
-    case 256: return launch(k_fwd_x<T, 256>, grid, block, lds, s, pd);
-    case 512: return launch(k_fwd_x<T, 512>, grid, block, lds, s, pd);
-    case 1024: return launch(k_fwd_x<T, 1024>, grid, block, lds, s, pd);
-    default: return launch(k_fwd_x<T, 0>, grid, block, lds, s, pd);
-  }
+  CS3D_DISPATCH(run_x_fwd_t, p->fx, p, pd, nrhs, s)
 }
-
 template <typename T>
 static hipError_t run_x_inv(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid(p->ldy / kTileJ, p->d.nz, nrhs), block(1024);
-  const size_t lds = lds_bytes_x<T>(p);
-  switch (p->fx) {
-    case 64: return launch(k_inv_x<T, 64>, grid, block, lds, s, pd);
-    case 128: return launch(k_inv_x<T, 128>, grid, block, lds, s, pd);
-    case 256: return launch(k_inv_x<T, 256>, grid, block, lds, s, pd);
-    case 512: return launch(k_inv_x<T, 512>, grid, block, lds, s, pd);
-    case 1024: return launch(k_inv_x<T, 1024>, grid, block, lds, s, pd);
-    default: return launch(k_inv_x<T, 0>, grid, block, lds, s, pd);
-  }
+  CS3D_DISPATCH(run_x_inv_t, p->fx, p, pd, nrhs, s)
 }
-
 template <typename T>
 static hipError_t run_y_fwd(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + kWavesY - 1) / kWavesY, nrhs), block(64 * kWavesY);
-  const size_t lds = lds_bytes_y<T>(p);
-  switch (p->fy) {
-    case 64: return launch(k_fwd_y<T, 64>, grid, block, lds, s, pd);
-    case 128: return launch(k_fwd_y<T, 128>, grid, block, lds, s, pd);
-    case 256: return launch(k_fwd_y<T, 256>, grid, block, lds, s, pd);
-    case 512: return launch(k_fwd_y<T, 512>, grid, block, lds, s, pd);
-    case 1024: return launch(k_fwd_y<T, 1024>, grid, block, lds, s, pd);
-    default: return launch(k_fwd_y<T, 0>, grid, block, lds, s, pd);
-  }
+  CS3D_DISPATCH(run_y_fwd_t, p->fy, p, pd, nrhs, s)
 }
-
 template <typename T>
 static hipError_t run_y_back(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + kWavesY - 1) / kWavesY, nrhs), block(64 * kWavesY);
-  const size_t lds = lds_bytes_y<T>(p);
-  switch (p->fy) {
-    case 64: return launch(k_back_y<T, 64>, grid, block, lds, s, pd);
-    case 128: return launch(k_back_y<T, 128>, grid, block, lds, s, pd);
-    case 256: return launch(k_back_y<T, 256>, grid, block, lds, s, pd);
-    case 512: return launch(k_back_y<T, 512>, grid, block, lds, s, pd);
-    case 1024: return launch(k_back_y<T, 1024>, grid, block, lds, s, pd);
-    default: return launch(k_back_y<T, 0>, grid, block, lds, s, pd);
-  }
+  CS3D_DISPATCH(run_y_back_t, p->fy, p, pd, nrhs, s)
+}
+#undef CS3D_DISPATCH
+
+static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  const int nzc = (p->d.nz + kZChunk - 1) / kZChunk;
+  dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
+  if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, pd);
+  return hipGetLastError();
 }
 
-static ProbDev make_pd(const cs3d_plan p, const double* f, int assembled, const double* glo,
-                       const double* ghi, double* u, int nrhs) {
+static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, const double* ghi,
+                       const double* F, double* u, int nrhs) {
   ProbDev pd{};
   pd.nx = p->d.nx;
   pd.ny = p->d.ny;
@@ -444,20 +473,19 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, int assembled, const 
   pd.sinx = p->dsinx;
   pd.siny = p->dsiny;
   pd.f = f;
-  pd.assembled = assembled;
-  const long long nin = (long long)p->d.nx * p->d.ny * p->d.nz;
-  pd.f_stride = assembled ? nin : (long long)(p->d.nx + 2) * (p->d.ny + 2) * (p->d.nz + 2);
+  pd.f_stride = (long long)(p->d.nx + 2) * (p->d.ny + 2) * (p->d.nz + 2);
   pd.glo = glo;
   pd.ghi = ghi;
   pd.g_stride = (long long)(p->d.nx + 2) * (p->d.ny + 2);
+  pd.F = F;
   pd.u = u;
-  pd.u_stride = nin;
+  pd.u_stride = (long long)p->d.nx * p->d.ny * p->d.nz;
   pd.G = p->ws;
   pd.G_stride = (long long)g_elems(p);
-  pd.C = reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) +
-                                   round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs));
+  pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) +
+                                           round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs))
+               : nullptr;
   pd.stats = p->dstats;
-  (void)nrhs;
   return pd;
 }
 
@@ -467,19 +495,25 @@ static hipError_t mark(cs3d_plan p, int k, hipStream_t s) {
   return hipEventRecord(p->ring[slot], s);
 }
 
+// FP64 path: [K0 RHS] -> K1 -> K2 -> K3 -> K4.  With an assembled F, K0 is skipped.
 template <typename T>
-static hipError_t solve_passes(cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+static hipError_t solve_passes(cs3d_plan p, const ProbDev& pd, int nrhs, bool with_rhs, hipStream_t s) {
   hipError_t e;
-  p->nstages = 4;
-  if ((e = mark(p, 0, s)) != hipSuccess) return e;
+  int k = 0;
+  p->nstages = with_rhs ? 5 : 4;
+  if ((e = mark(p, k++, s)) != hipSuccess) return e;
+  if (with_rhs) {
+    if ((e = run_rhs(p, pd, nrhs, s)) != hipSuccess) return e;
+    if ((e = mark(p, k++, s)) != hipSuccess) return e;
+  }
   if ((e = run_x_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, 1, s)) != hipSuccess) return e;
+  if ((e = mark(p, k++, s)) != hipSuccess) return e;
   if ((e = run_y_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, 2, s)) != hipSuccess) return e;
+  if ((e = mark(p, k++, s)) != hipSuccess) return e;
   if ((e = run_y_back<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, 3, s)) != hipSuccess) return e;
+  if ((e = mark(p, k++, s)) != hipSuccess) return e;
   if ((e = run_x_inv<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, 4, s)) != hipSuccess) return e;
+  if ((e = mark(p, k++, s)) != hipSuccess) return e;
   ++p->solves;
   return hipSuccess;
 }
@@ -491,13 +525,15 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
   if (!p->ws || p->ws_bytes < cs3d_workspace_bytes(p, nrhs)) return CS3D_E_WORKSPACE;
   if (p->d.precision != CS3D_FP64) return CS3D_E_UNSUPPORTED;
+  if (assembled && f == u) return CS3D_E_INVAL;  // F must stay intact until K1 has read all of it
   hipStream_t s = (hipStream_t)hip_stream;
   p->last_stream = s;
-  const ProbDev pd = make_pd(p, f, assembled, glo, ghi, u, nrhs);
+  // the interior F lives in u: K0 writes it there, K1 reads it, K4 overwrites it with the solution
+  const ProbDev pd = make_pd(p, assembled ? nullptr : f, glo, ghi, assembled ? f : u, u, nrhs);
   if (hipEventRecord(p->ev0, s) != hipSuccess) return CS3D_E_DEVICE;
   k_stats_reset<<<1, 64, 0, s>>>(p->dstats);
   if (hipGetLastError() != hipSuccess) return CS3D_E_DEVICE;
-  if (solve_passes<double>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+  if (solve_passes<double>(p, pd, nrhs, !assembled, s) != hipSuccess) return CS3D_E_DEVICE;
   if (hipEventRecord(p->ev1, s) != hipSuccess) return CS3D_E_DEVICE;
   p->timed = true;
   return CS3D_OK;
@@ -519,11 +555,15 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   if (!p || !dev_f || !dev_u || !dev_r) return CS3D_E_INVAL;
   if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
+  if (dev_r == dev_u || dev_r == dev_f) return CS3D_E_INVAL;
   hipStream_t s = (hipStream_t)hip_stream;
-  const ProbDev pd = make_pd(p, dev_f, assembled, dev_g_lo, dev_g_hi, nullptr, nrhs);
+  // F (with the lift) goes into r, then r = F - A U in place
+  const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
+  if (!assembled && run_rhs(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
   dim3 grid((p->d.nx + 63) / 64, (p->d.ny + 3) / 4, p->d.nz * nrhs);
-  if (grid.z > 65535u) return CS3D_E_UNSUPPORTED;
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, pd, dev_u, dev_r);
+  if (grid.z > 65535u || grid.y > 65535u) return CS3D_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, pd, assembled ? dev_f : (const double*)dev_r, dev_u,
+                     dev_r);
   return hipGetLastError() == hipSuccess ? CS3D_OK : CS3D_E_DEVICE;
 }
 

@@ -1,21 +1,23 @@
-// kernels.hpp - the four streaming passes of the direct solve (Section 3.6) on CDNA4.
+// kernels.hpp - the streaming passes of the direct solve (Section 3.6) on CDNA4.
 //
-//  K1 fwd_x   : RHS operator (Sections 3.2-3.5) + z-face lift + DST-I along x of
-//               16 x-lines per workgroup; the results are transposed through LDS and
-//               stored as y-lines  G[l][n][j]  (j fastest, 128-byte rows).
-//  K2 fwd_y   : one wavefront per x-mode n marches l = 1..N_z: DST-I along y of the
-//               line G[l][n][:], modal eigenvalues lambda^{-,0,+} from the row weights
-//               (built on the fly), forward elimination of the N_y tridiagonal systems
-//               (one mode m per lane slot).  d'_l is stored in place, c'_l once per plan
-//               column in C.
-//  K3 back_y  : the same wavefronts march l = N_z..1: back substitution
+//  K0 rhs     : RHS operator of the scheme (Sections 3.2-3.5) + z-face lift, written as
+//               the interior array F (into the caller's output buffer).  Workgroups
+//               march along z over a 64 x 16 tile, keeping five planes (with a halo of
+//               two) in LDS, so f is read from HBM about once.
+//  K1 fwd_x   : DST-I along x of 16 x-lines of F per workgroup; the results are
+//               transposed through LDS and stored as y-lines G[l][n][j] (j fastest).
+//  K2 fwd_y   : one line group (one or two wavefronts) per x-mode n marches l = 1..N_z:
+//               DST-I along y of G[l][n][:], modal eigenvalues lambda^{-,0,+} built on the
+//               fly, forward elimination of the N_y tridiagonal systems (one mode m per
+//               lane slot).  d'_l is stored in place, c'_l once per plan column in C.
+//  K3 back_y  : the same line groups march l = N_z..1: back substitution
 //               W_l = d'_l - c'_l W_{l+1}, inverse DST-I along y, stored in place.
-//  K4 inv_x   : 16 y-lines per workgroup are transposed back through LDS, inverse
+//  K4 inv_x   : 8 y-lines per workgroup are transposed back through LDS, inverse
 //               DST-I along x, scaled by 4/((N_x+1)(N_y+1)) and stored as u (x fastest).
 //
-// The DST-I is its own inverse up to the factor (N+1)/2, so the four line
-// transforms are the same routine and the orthonormal V of Section 3.6 is
-// recovered by the single final scale.
+// The DST-I is its own inverse up to the factor (N+1)/2, so all line transforms are
+// the same routine and the orthonormal V of Section 3.6 is recovered by the single
+// final scale.
 #pragma once
 #include "wave_dst.hpp"
 
@@ -23,8 +25,8 @@ namespace cs3d {
 
 enum SchemeId : int { kHelm2 = 2, kHelm4 = 4, kHelm6 = 6, kCd4 = 14, kWeights = 99 };
 
-constexpr int kTileJ = 16;     // y-lines per K1/K4 workgroup (128-byte rows of doubles)
-constexpr int kWavesY = 4;     // x-modes (wavefronts) per K2/K3 workgroup
+constexpr int kTileJ = 8;     // y-lines per K1/K4 workgroup (one wavefront each)
+constexpr int kBlockY = 256;  // threads per K2/K3 workgroup
 
 struct ProbDev {
   int nx, ny, nz;
@@ -40,102 +42,86 @@ struct ProbDev {
   const double* k2z;   // [nz+2]
   const double* ctx;   // 1 - cos(pi n/Mx), n = 1..nx   [nx]
   const double* cty;   // 1 - cos(pi m/My), m = 1..ny   [ny]
-  const double2* twx;  // exp(-i pi k/Mx), k < 2 Mx  (FFT path)
+  const double2* twx;  // exp(-i pi k/Mx), k < Mx  (FFT path)
   const double2* twy;
   const double* sinx;  // sin(pi r/Mx), r < 2 Mx      (dense path)
   const double* siny;
   // data (per right-hand side strides in elements)
-  const double* f;     // closed grid, or interior F when assembled
+  const double* f;     // closed grid f (K0 input)
   long long f_stride;
   const double* glo;   // closed planes or null
   const double* ghi;
   long long g_stride;
-  double* u;           // interior
+  const double* F;     // interior right-hand side (K1 input)
+  double* u;           // interior solution (K4 output; K0 writes F here)
   long long u_stride;
   void* G;             // [nrhs][nz][nx][ldy] of the transform type
   long long G_stride;
   double* C;           // [nz][nx][ldy]   c' of the tridiagonal LU
   unsigned long long* stats;  // [0] = bits of min |pivot|, [1] = count of bad pivots
-  int assembled;
 };
 
-template <int M>
+// ---------------------------------------------------------------------------
+// Line transform selection: M = N+1 for the FFT path, 0 for dense sine sums.
+// ---------------------------------------------------------------------------
+template <int M, int WPL>
 struct Tx {
-  static constexpr int NS = FftGeom<M>::R;
+  static constexpr int NS = FftGeom<M, WPL>::R;
 };
-template <>
-struct Tx<0> {
+template <int WPL>
+struct Tx<0, WPL> {
   static constexpr int NS = kDenseSlots;
 };
 
-template <typename T, int M>
-__device__ __forceinline__ void line_dst(T* buf, int N, T (&out)[Tx<M>::NS], int lane,
-                                         const double2* tw, const double* sintab) {
+template <typename T, int M, int WPL>
+using TxOut = T[Tx<M, WPL>::NS];
+
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void line_dst(T* buf, int N, TxOut<T, M, WPL>& out, int tl, const cx<T>* tab,
+                                         const double* sintab) {
   if constexpr (M == 0) {
-    dst_dense<T>(buf, N, out, lane, sintab);
+    dst_dense<T>(buf, N, out, tl, sintab);
   } else {
-    dst_fft<T, M>(buf, out, lane, tw);
+    dst_fft<T, M, WPL>(buf, out, tl, tab);
   }
 }
 
-template <int M>
-__device__ __forceinline__ int line_mode(int lane, int s, int N) {
+template <int M, int WPL>
+__device__ __forceinline__ int line_mode(int tl, int s, int N) {
   if constexpr (M == 0) {
-    return dense_mode(lane, s, N);
+    return dense_mode(tl, s, N);
   } else {
-    return fft_mode<M>(lane, s);
+    return fft_mode<M, WPL>(tl, s);
   }
 }
 
-// elements of T in one wave's LDS line region
+// elements of T in one line buffer
 template <typename T, int M>
-__host__ __device__ constexpr int region_elems(int N) {
-  return M ? (M * 8) / (int)sizeof(T) : ((N + 1 + 63) / 64) * 64;
+__host__ __device__ constexpr int line_buf_elems(int N) {
+  return M ? fft_buf_elems<T, M>() : lp(((N + 1 + 63) / 64) * 64);
 }
+
+// twiddle table bytes (FFT path only)
+template <typename T, int M>
+__host__ __device__ constexpr int tw_bytes() {
+  return M ? tw_entries<M>() * (int)sizeof(cx<T>) : 0;
+}
+
+// odd row stride (>= nx + 1) of the K1/K4 transpose tile
+__host__ __device__ constexpr int tile_stride(int nx) { return (nx & 1) ? nx + 2 : nx + 1; }
 
 // ---------------------------------------------------------------------------
-// RHS operator at interior point (i, j, l) from f on the closed grid.
+// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 256 threads
+// (64 x 4, four y-rows each), marching over kZChunk planes.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double d4_axis(const double* c, long long s, int i, int n) {
-  // fourth difference along one axis: central inside, one-sided 6-point at the
-  // first and last interior layer (needs n >= 4)
-  if (i >= 2 && i <= n - 1)
-    return c[-2 * s] - 4.0 * c[-s] + 6.0 * c[0] - 4.0 * c[s] + c[2 * s];
-  if (i == 1)
-    return 2.0 * c[-s] - 9.0 * c[0] + 16.0 * c[s] - 14.0 * c[2 * s] + 6.0 * c[3 * s] - c[4 * s];
-  return 2.0 * c[s] - 9.0 * c[0] + 16.0 * c[-s] - 14.0 * c[-2 * s] + 6.0 * c[-3 * s] - c[-4 * s];
-}
+constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;
+constexpr int kSX = kRX + 2 * kRH, kSY = kRY + 2 * kRH;
 
-__device__ __forceinline__ double rhs_point(const ProbDev& p, const double* __restrict__ f, int i,
-                                            int j, int l) {
-  const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
-  const double* c = f + i + sy * j + sz * l;
-  const double f0 = c[0];
-  const double hz2 = p.hz * p.hz;
-  if (p.scheme == kHelm2) return hz2 * f0;
-  const double d2x = c[-1] + c[1] - 2.0 * f0;
-  const double d2y = c[-sy] + c[sy] - 2.0 * f0;
-  const double d2z = c[-sz] + c[sz] - 2.0 * f0;
-  if (p.scheme == kHelm4) return hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
-  if (p.scheme == kCd4) {
-    const double dz1 = 0.5 * (c[sz] - c[-sz]);
-    return hz2 * (f0 + (d2x + d2y) * (1.0 / 12.0) + (p.hz * p.gamma * dz1 + d2z) * (1.0 / 12.0));
-  }
-  // kHelm6: f + h^2/12 sum d2 - h^4/240 sum d4 + h^4/90 sum d2d2 - h^2 k^2 f/20
-  //         + h^4 (k^2)_z f_z / 60, every difference undivided (h folded in).
-  const double d4 = d4_axis(c, 1, i, p.nx) + d4_axis(c, sy, j, p.ny) + d4_axis(c, sz, l, p.nz);
-  const double exy = c[-sy - 1] + c[-sy + 1] + c[sy - 1] + c[sy + 1];
-  const double exz = c[-sz - 1] + c[-sz + 1] + c[sz - 1] + c[sz + 1];
-  const double eyz = c[-sz - sy] + c[-sz + sy] + c[sz - sy] + c[sz + sy];
-  const double ax = c[-1] + c[1], ay = c[-sy] + c[sy], az = c[-sz] + c[sz];
-  const double dxy = exy - 2.0 * (ax + ay) + 4.0 * f0;
-  const double dxz = exz - 2.0 * (ax + az) + 4.0 * f0;
-  const double dyz = eyz - 2.0 * (ay + az) + 4.0 * f0;
-  const double h = p.hz;
-  const double kl = p.k2[l], kzl = p.k2z[l];
-  return hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - d4 * (1.0 / 240.0) +
-                (dxy + dxz + dyz) * (1.0 / 90.0) - h * h * kl * f0 * (1.0 / 20.0) +
-                h * h * h * kzl * (c[sz] - c[-sz]) * (1.0 / 120.0));
+__device__ __forceinline__ double d4_onesided(const double* c, long long s, bool low) {
+  // fourth difference at the first (low) or last interior layer: one-sided 6-point
+  // formula from the boundary point and the next five points
+  return low ? 2.0 * c[-s] - 9.0 * c[0] + 16.0 * c[s] - 14.0 * c[2 * s] + 6.0 * c[3 * s] - c[4 * s]
+             : 2.0 * c[s] - 9.0 * c[0] + 16.0 * c[-s] - 14.0 * c[-2 * s] + 6.0 * c[-3 * s] - c[-4 * s];
 }
 
 // in-plane 9-point stencil of weights w = (a, b, c, d) on a closed plane at (i, j)
@@ -147,57 +133,199 @@ __device__ __forceinline__ double plane9(const double* __restrict__ w, const dou
          w[2] * (c[-sy] + c[sy]) + w[3] * c[0];
 }
 
-__device__ __forceinline__ double assembled_rhs(const ProbDev& p, int r, int i, int j, int l) {
-  if (p.assembled)
-    return p.f[r * p.f_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))];
-  double F = rhs_point(p, p.f + r * p.f_stride, i, j, l);
-  if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
-  if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
-  return F;
+constexpr int kRLoads = (kSY * kSX + 255) / 256;  // plane-tile elements per thread
+
+__global__ void __launch_bounds__(256) k_rhs(ProbDev p) {
+  __shared__ double win[5][kSY * kSX];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
+  const int nzc = (p.nz + kZChunk - 1) / kZChunk;
+  const int zc = blockIdx.z % nzc, r = blockIdx.z / nzc;
+  const int lb = 1 + zc * kZChunk;
+  const int le = min(p.nz, lb + kZChunk - 1);
+  const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
+  const double* __restrict__ f = p.f + r * p.f_stride;
+  const int halo = (p.scheme == kHelm6) ? 2 : 1;
+
+  // this thread's share of a plane tile: in-plane offsets, fixed for every plane
+  long long off[kRLoads];
+  bool ok[kRLoads];
+#pragma unroll
+  for (int k = 0; k < kRLoads; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    const int yy = e / kSX, xx = e - yy * kSX;
+    const int gx = x0 - kRH + xx, gy = y0 - kRH + yy;
+    ok[k] = e < kSY * kSX && gx >= 0 && gx <= p.nx + 1 && gy >= 0 && gy <= p.ny + 1;
+    off[k] = ok[k] ? gx + sy * gy : 0;
+  }
+  double pre[kRLoads];
+  auto fetch = [&](int q) {
+    const bool qok = q >= 0 && q <= p.nz + 1;
+#pragma unroll
+    for (int k = 0; k < kRLoads; ++k) pre[k] = (qok && ok[k]) ? f[off[k] + sz * q] : 0.0;
+  };
+  auto stash = [&](int q) {
+    double* w = win[(q + 5) % 5];
+#pragma unroll
+    for (int k = 0; k < kRLoads; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < kSY * kSX) w[e] = pre[k];
+    }
+  };
+  for (int q = lb - halo; q < lb + halo; ++q) {
+    fetch(q);
+    stash(q);
+  }
+  fetch(lb + halo);
+
+  const int i = x0 + tx;
+  const double hz2 = p.hz * p.hz;
+  for (int l = lb; l <= le; ++l) {
+    stash(l + halo);
+    __syncthreads();
+    if (l < le) fetch(l + halo + 1);  // in flight while this plane is computed
+    const double* P0 = win[(l + 5) % 5];
+    const double* Pm = win[(l + 4) % 5];
+    const double* Pp = win[(l + 6) % 5];
+    const double* Pmm = win[(l + 3) % 5];
+    const double* Ppp = win[(l + 7) % 5];
+    const double kl = p.k2[l], kzl = p.k2z[l];
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      const int yl = ty * 4 + k, j = y0 + yl;
+      if (i > p.nx || j > p.ny) continue;
+      const int c0 = (yl + kRH) * kSX + tx + kRH;  // tile index of (i, j)
+      const double f0 = P0[c0];
+      double F;
+      if (p.scheme == kHelm2) {
+        F = hz2 * f0;
+      } else {
+        const double ax = P0[c0 - 1] + P0[c0 + 1];
+        const double ay = P0[c0 - kSX] + P0[c0 + kSX];
+        const double az = Pm[c0] + Pp[c0];
+        const double d2x = ax - 2.0 * f0, d2y = ay - 2.0 * f0, d2z = az - 2.0 * f0;
+        if (p.scheme == kHelm4) {
+          F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
+        } else if (p.scheme == kCd4) {
+          const double dz1 = 0.5 * (Pp[c0] - Pm[c0]);
+          F = hz2 * (f0 + (d2x + d2y) * (1.0 / 12.0) + (p.hz * p.gamma * dz1 + d2z) * (1.0 / 12.0));
+        } else {
+          // 6th order: f + h^2/12 sum d2 - h^4/240 sum d4 + h^4/90 sum d2d2 - h^2 k^2 f/20
+          //            + h^4 (k^2)_z f_z/60, differences undivided
+          const double* c = f + i + sy * j + sz * l;
+          const double d4x = (i >= 2 && i <= p.nx - 1)
+                                 ? P0[c0 - 2] - 4.0 * P0[c0 - 1] + 6.0 * f0 - 4.0 * P0[c0 + 1] + P0[c0 + 2]
+                                 : d4_onesided(c, 1, i == 1);
+          const double d4y = (j >= 2 && j <= p.ny - 1)
+                                 ? P0[c0 - 2 * kSX] - 4.0 * P0[c0 - kSX] + 6.0 * f0 - 4.0 * P0[c0 + kSX] +
+                                       P0[c0 + 2 * kSX]
+                                 : d4_onesided(c, sy, j == 1);
+          const double d4z = (l >= 2 && l <= p.nz - 1)
+                                 ? Pmm[c0] - 4.0 * Pm[c0] + 6.0 * f0 - 4.0 * Pp[c0] + Ppp[c0]
+                                 : d4_onesided(c, sz, l == 1);
+          const double exy = P0[c0 - kSX - 1] + P0[c0 - kSX + 1] + P0[c0 + kSX - 1] + P0[c0 + kSX + 1];
+          const double exz = Pm[c0 - 1] + Pm[c0 + 1] + Pp[c0 - 1] + Pp[c0 + 1];
+          const double eyz = Pm[c0 - kSX] + Pm[c0 + kSX] + Pp[c0 - kSX] + Pp[c0 + kSX];
+          const double dxy = exy - 2.0 * (ax + ay) + 4.0 * f0;
+          const double dxz = exz - 2.0 * (ax + az) + 4.0 * f0;
+          const double dyz = eyz - 2.0 * (ay + az) + 4.0 * f0;
+          const double h = p.hz;
+          F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - (d4x + d4y + d4z) * (1.0 / 240.0) +
+                     (dxy + dxz + dyz) * (1.0 / 90.0) - h * h * kl * f0 * (1.0 / 20.0) +
+                     h * h * h * kzl * (Pp[c0] - Pm[c0]) * (1.0 / 120.0));
+        }
+      }
+      if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
+      if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
+      p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] = F;
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
-// K1: RHS + lift + DST along x, transposed store into y-lines.
+// K1: DST along x of 8 lines of F, transposed store into y-lines.  Persistent:
+// each workgroup walks tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... (8 y-lines
+// of one plane of one right-hand side each) and loads the rows of its next tile
+// into registers while it transforms the current one.
+// LDS: 8 line buffers (the transpose tile overlays them) + twiddle table.
 // ---------------------------------------------------------------------------
+constexpr int kNV = 16;  // ceil(1023/64): row values per lane
+
+struct XTile {
+  int jt, l, r, j;
+  bool active;
+};
+
+__device__ __forceinline__ XTile decode_xtile(const ProbDev& p, int t, int w) {
+  const int njt = p.ldy / kTileJ;
+  XTile x;
+  x.jt = t % njt;
+  x.l = (t / njt) % p.nz + 1;
+  x.r = t / (njt * p.nz);
+  x.j = x.jt * kTileJ + w;
+  x.active = x.j >= 1 && x.j <= p.ny;
+  return x;
+}
+
 template <typename T, int MX>
-__global__ void __launch_bounds__(1024) k_fwd_x(ProbDev p) {
+__global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MX>::NS;
-  const int jt = blockIdx.x, l = blockIdx.y + 1, r = blockIdx.z;
+  constexpr int NS = Tx<MX, 1>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int reg = region_elems<T, MX>(p.nx);
-  T* buf = smem + w * reg;
-  const int j = jt * kTileJ + w;
-  const bool active = (j >= 1 && j <= p.ny);
-  T out[NS];
-  if (active) {
-    if (lane == 0) buf[0] = (T)0;
-    for (int i = 1 + lane; i <= p.nx; i += 64) buf[i] = (T)assembled_rhs(p, r, i, j, l);
-    wave_sync();
-    line_dst<T, MX>(buf, p.nx, out, lane, p.twx, p.sinx);
-  }
-  __syncthreads();
-  // tile[n-1][jj ^ ((n-1) & 15)]
-  if (active) {
+  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int ts = tile_stride(p.nx);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * bufn);
+  if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
+  T* buf = smem + w * bufn;
+  double pre[kNV];
+  auto fetch = [&](int t) {
+    const XTile x = decode_xtile(p, t, w);
+    const double* Fr = p.F + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int n = line_mode<MX>(lane, s, p.nx);
-      if (n > 0) smem[(n - 1) * kTileJ + (w ^ ((n - 1) & 15))] = out[s];
+    for (int k = 0; k < kNV; ++k) {
+      const int i = 1 + lane + 64 * k;
+      pre[k] = (x.active && i <= p.nx) ? Fr[i - 1] : 0.0;
     }
-  } else {
-    for (int n = 1 + lane; n <= p.nx; n += 64) smem[(n - 1) * kTileJ + (w ^ ((n - 1) & 15))] = (T)0;
-  }
-  __syncthreads();
-  T* G = reinterpret_cast<T*>(p.G) + r * p.G_stride + (long long)(l - 1) * p.nx * p.ldy + jt * kTileJ;
-  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
-    const int n0 = idx / kTileJ, jj = idx % kTileJ;
-    G[(long long)n0 * p.ldy + jj] = smem[n0 * kTileJ + (jj ^ (n0 & 15))];
+  };
+  int t = blockIdx.x;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
+    const XTile x = decode_xtile(p, t, w);
+    __syncthreads();  // the previous tile's store phase is done with the LDS
+    if (lane == 0) buf[lp(0)] = (T)0;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      const int i = 1 + lane + 64 * k;
+      if (i <= p.nx) buf[lp(i)] = (T)pre[k];
+    }
+    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
+    __syncthreads();  // also publishes the twiddle table on the first pass
+    T out[NS];
+    if (x.active) line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
+    __syncthreads();
+    // tile[jj][n], n = 1..nx, odd row stride
+    if (x.active) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int n = line_mode<MX, 1>(lane, s, p.nx);
+        if (n > 0) smem[w * ts + n] = out[s];
+      }
+    } else {
+      for (int n = 1 + lane; n <= p.nx; n += 64) smem[w * ts + n] = (T)0;
+    }
+    __syncthreads();
+    T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
+    for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
+      const int n0 = idx / kTileJ, jj = idx % kTileJ;
+      G[(long long)n0 * p.ldy + jj] = smem[jj * ts + n0 + 1];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// K2: DST along y + modal eigenvalues + forward elimination (one wave per x-mode).
+// K2: DST along y + modal eigenvalues + forward elimination.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void record_pivot(double piv, double& minpiv, unsigned& bad) {
   const double a = fabs(piv);
@@ -220,23 +348,39 @@ __device__ __forceinline__ void flush_stats(const ProbDev& p, double minpiv, uns
   }
 }
 
+// waves per line in the y passes: two for the 1024-point FFT, one otherwise
+template <int MY>
+struct YCfg {
+  static constexpr int WPL = (MY == 1024) ? 2 : 1;
+  static constexpr int LANES = 64 * WPL;
+  static constexpr int LPB = kBlockY / LANES;  // lines (x-modes) per workgroup
+  static constexpr int NS = Tx<MY, WPL>::NS;
+  static constexpr int NLD = (MY ? MY : 1024) / LANES;  // line values loaded per lane
+};
+
 template <typename T, int MY>
-__global__ void __launch_bounds__(64 * kWavesY) k_fwd_y(ProbDev p) {
+__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p) {
+  using C = YCfg<MY>;
+  constexpr int NS = C::NS, WPL = C::WPL;
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MY>::NS;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int n = blockIdx.x * kWavesY + w + 1, r = blockIdx.y;
-  if (n > p.nx) return;  // whole wave leaves; no workgroup barrier below
-  const int reg = region_elems<T, MY>(p.ny);
-  T* buf = smem + w * reg;
-  const double ctn = p.ctx[n - 1];
-  int mpos[NS];
-  double cph[NS], cp[NS], dp[NS];
+  const int bufn = line_buf_elems<T, MY>(p.ny);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + C::LPB * bufn);
+  if constexpr (MY != 0) {
+    load_twiddles<T, MY, WPL>(tab, p.twy);
+    __syncthreads();
+  }
+  const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
+  const int n = blockIdx.x * C::LPB + line + 1, r = blockIdx.y;
+  const bool active = n <= p.nx;
+  if constexpr (WPL == 1) {
+    if (!active) return;  // no workgroup barrier below for single-wave lines
+  }
+  T* buf = smem + line * bufn;
+  const double ctn = active ? p.ctx[n - 1] : 0.0;
+  double cp[NS], dp[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    mpos[s] = line_mode<MY>(lane, s, p.ny);
-    cph[s] = mpos[s] > 0 ? p.cty[mpos[s] - 1] : 0.0;
     cp[s] = 0.0;
     dp[s] = 0.0;
   }
@@ -244,135 +388,212 @@ __global__ void __launch_bounds__(64 * kWavesY) k_fwd_y(ProbDev p) {
   unsigned bad = 0;
   T* Gr = reinterpret_cast<T*>(p.G) + r * p.G_stride;
   const bool write_c = (r == 0);
+  const long long lstride = (long long)p.nx * p.ldy;
+  const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
+  // prefetch of the first line
+  T pre[C::NLD];
+#pragma unroll
+  for (int s = 0; s < C::NLD; ++s) {
+    const int e = tl + C::LANES * s;
+    pre[s] = (active && e <= p.ny) ? Gr[nbase + e] : (T)0;
+  }
   for (int l = 1; l <= p.nz; ++l) {
-    T* line = Gr + ((long long)(l - 1) * p.nx + (n - 1)) * p.ldy;
-    for (int e = lane; e < p.ldy && e <= p.ny; e += 64) buf[e] = line[e];
-    wave_sync();
+    T* line_p = Gr + (long long)(l - 1) * lstride + nbase;
+#pragma unroll
+    for (int s = 0; s < C::NLD; ++s) {
+      const int e = tl + C::LANES * s;
+      if (e <= p.ny) buf[lp(e)] = pre[s];
+    }
+    line_sync<WPL>();
+    if (l < p.nz) {
+#pragma unroll
+      for (int s = 0; s < C::NLD; ++s) {
+        const int e = tl + C::LANES * s;
+        pre[s] = (active && e <= p.ny) ? line_p[lstride + e] : (T)0;
+      }
+    }
     T out[NS];
-    line_dst<T, MY>(buf, p.ny, out, lane, p.twy, p.siny);
+    line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
     // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
     const double* Ll = p.LC + (l - 1) * 12;
     const double bm = Ll[0] + ctn * Ll[1], am = Ll[2] + Ll[3] * ctn;
     const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
     const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
-    double* Cl = p.C + ((long long)(l - 1) * p.nx + (n - 1)) * p.ldy;
+    double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
+    if (active) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (mpos[s] > 0) {
-        const double lm = am * cph[s] + bm, l0 = a0 * cph[s] + b0, lp = ap * cph[s] + bp;
-        const double piv = l0 - lm * cp[s];
-        record_pivot(piv, minpiv, bad);
-        const double inv = 1.0 / piv;
-        cp[s] = lp * inv;
-        dp[s] = ((double)out[s] - lm * dp[s]) * inv;
-        line[mpos[s]] = (T)dp[s];
-        if (write_c) Cl[mpos[s]] = cp[s];
+      for (int s = 0; s < NS; ++s) {
+        const int m = line_mode<MY, WPL>(tl, s, p.ny);
+        if (m > 0) {
+          const double sm = p.cty[m - 1];
+          const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+          const double piv = l0 - lm * cp[s];
+          record_pivot(piv, minpiv, bad);
+          const double inv = 1.0 / piv;
+          cp[s] = lpv * inv;
+          dp[s] = ((double)out[s] - lm * dp[s]) * inv;
+          line_p[m] = (T)dp[s];
+          if (write_c) Cl[m] = cp[s];
+        }
       }
     }
-    wave_sync();
+    line_sync<WPL>();
   }
-  flush_stats(p, minpiv, bad);
+  if (active || WPL > 1) flush_stats(p, minpiv, bad);
 }
 
 // ---------------------------------------------------------------------------
-// K3: back substitution + inverse DST along y (one wave per x-mode).
+// K3: back substitution + inverse DST along y.
 // ---------------------------------------------------------------------------
 template <typename T, int MY>
-__global__ void __launch_bounds__(64 * kWavesY) k_back_y(ProbDev p) {
+__global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
+  using C = YCfg<MY>;
+  constexpr int NS = C::NS, WPL = C::WPL;
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MY>::NS;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int n = blockIdx.x * kWavesY + w + 1, r = blockIdx.y;
-  if (n > p.nx) return;
-  const int reg = region_elems<T, MY>(p.ny);
-  T* buf = smem + w * reg;
-  int mpos[NS];
+  const int bufn = line_buf_elems<T, MY>(p.ny);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + C::LPB * bufn);
+  if constexpr (MY != 0) {
+    load_twiddles<T, MY, WPL>(tab, p.twy);
+    __syncthreads();
+  }
+  const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
+  const int n = blockIdx.x * C::LPB + line + 1, r = blockIdx.y;
+  const bool active = n <= p.nx;
+  if constexpr (WPL == 1) {
+    if (!active) return;
+  }
+  T* buf = smem + line * bufn;
   double Wn[NS];
+  int mpos[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    mpos[s] = line_mode<MY>(lane, s, p.ny);
+    mpos[s] = active ? line_mode<MY, WPL>(tl, s, p.ny) : -1;
     Wn[s] = 0.0;
   }
   T* Gr = reinterpret_cast<T*>(p.G) + r * p.G_stride;
+  const long long lstride = (long long)p.nx * p.ldy;
+  const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
+  // prefetch d' and c' of the last plane
+  T pd[NS];
+  double pc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const long long off = (long long)(p.nz - 1) * lstride + nbase + mpos[s];
+    pd[s] = mpos[s] > 0 ? Gr[off] : (T)0;
+    pc[s] = mpos[s] > 0 ? p.C[off] : 0.0;
+  }
   for (int l = p.nz; l >= 1; --l) {
-    T* line = Gr + ((long long)(l - 1) * p.nx + (n - 1)) * p.ldy;
-    const double* Cl = p.C + ((long long)(l - 1) * p.nx + (n - 1)) * p.ldy;
+    T* line_p = Gr + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (mpos[s] > 0) {
-        Wn[s] = (double)line[mpos[s]] - Cl[mpos[s]] * Wn[s];
-        buf[mpos[s]] = (T)Wn[s];
+        Wn[s] = (double)pd[s] - pc[s] * Wn[s];
+        buf[lp(mpos[s])] = (T)Wn[s];
       }
     }
-    if (lane == 0) buf[0] = (T)0;
-    wave_sync();
+    if (tl == 0) buf[lp(0)] = (T)0;
+    line_sync<WPL>();
+    if (l > 1) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const long long off = (long long)(l - 2) * lstride + nbase + mpos[s];
+        pd[s] = mpos[s] > 0 ? Gr[off] : (T)0;
+        pc[s] = mpos[s] > 0 ? p.C[off] : 0.0;
+      }
+    }
     T out[NS];
-    line_dst<T, MY>(buf, p.ny, out, lane, p.twy, p.siny);
+    line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (mpos[s] > 0) line[mpos[s]] = out[s];
-    wave_sync();
+      if (mpos[s] > 0) line_p[mpos[s]] = out[s];
+    line_sync<WPL>();
   }
 }
 
 // ---------------------------------------------------------------------------
-// K4: transposed load of 16 y-lines, inverse DST along x, scale, store u.
+// K4: transposed load of 8 y-lines, inverse DST along x, scale, store u.
+// Persistent like K1: the next tile's y-line segments are loaded into registers
+// while the current tile is transformed.
 // ---------------------------------------------------------------------------
 template <typename T, int MX>
-__global__ void __launch_bounds__(1024) k_inv_x(ProbDev p) {
+__global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MX>::NS;
-  constexpr int NV = 16;  // ceil(1024/64) column values per lane
-  const int jt = blockIdx.x, l = blockIdx.y + 1, r = blockIdx.z;
+  constexpr int NS = Tx<MX, 1>::NS;
+  constexpr int NT = (1023 * kTileJ + 64 * kTileJ - 1) / (64 * kTileJ);  // segment values per thread
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const T* G = reinterpret_cast<const T*>(p.G) + r * p.G_stride + (long long)(l - 1) * p.nx * p.ldy +
-               jt * kTileJ;
-  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
-    const int n0 = idx / kTileJ, jj = idx % kTileJ;
-    smem[n0 * kTileJ + (jj ^ (n0 & 15))] = G[(long long)n0 * p.ldy + jj];
-  }
-  __syncthreads();
-  const int j = jt * kTileJ + w;
-  const bool active = (j >= 1 && j <= p.ny);
-  T col[NV];
+  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int ts = tile_stride(p.nx);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * bufn);
+  if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
+  T* buf = smem + w * bufn;
+  T pre[NT];
+  auto fetch = [&](int t) {
+    const XTile x = decode_xtile(p, t, 0);
+    const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
+                 x.jt * kTileJ;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const int n = 1 + lane + 64 * k;
-    col[k] = (active && n <= p.nx) ? smem[(n - 1) * kTileJ + (w ^ ((n - 1) & 15))] : (T)0;
-  }
-  __syncthreads();
-  if (!active) return;
-  const int reg = region_elems<T, MX>(p.nx);
-  T* buf = smem + w * reg;
+    for (int k = 0; k < NT; ++k) {
+      const int idx = threadIdx.x + 64 * kTileJ * k;
+      const int n0 = idx / kTileJ, jj = idx % kTileJ;
+      pre[k] = (n0 < p.nx) ? G[(long long)n0 * p.ldy + jj] : (T)0;
+    }
+  };
+  int t = blockIdx.x;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
+    const XTile x = decode_xtile(p, t, w);
+    __syncthreads();  // the previous transform is done with the LDS
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const int n = 1 + lane + 64 * k;
-    if (n <= p.nx) buf[n] = col[k];
-  }
-  if (lane == 0) buf[0] = (T)0;
-  wave_sync();
-  T out[NS];
-  line_dst<T, MX>(buf, p.nx, out, lane, p.twx, p.sinx);
-  double* u = p.u + r * p.u_stride + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+    for (int k = 0; k < NT; ++k) {
+      const int idx = threadIdx.x + 64 * kTileJ * k;
+      const int n0 = idx / kTileJ, jj = idx % kTileJ;
+      if (n0 < p.nx) smem[jj * ts + n0 + 1] = pre[k];
+    }
+    __syncthreads();
+    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
+    T col[kNV];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = line_mode<MX>(lane, s, p.nx);
-    if (i > 0) u[i - 1] = p.scale * (double)out[s];
+    for (int k = 0; k < kNV; ++k) {
+      const int n = 1 + lane + 64 * k;
+      col[k] = (x.active && n <= p.nx) ? smem[w * ts + n] : (T)0;
+    }
+    __syncthreads();
+    if (x.active) {
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        const int n = 1 + lane + 64 * k;
+        if (n <= p.nx) buf[lp(n)] = col[k];
+      }
+      if (lane == 0) buf[lp(0)] = (T)0;
+    }
+    wave_sync();
+    if (x.active) {
+      T out[NS];
+      line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
+      double* u = p.u + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int i = line_mode<MX, 1>(lane, s, p.nx);
+        if (i > 0) u[i - 1] = p.scale * (double)out[s];
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // FP64 residual r = F - A U of eq. stencil27 (z-face data as boundary planes).
+// F is the interior right-hand side (lift included).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_residual(ProbDev p, const double* __restrict__ U,
-                                                  double* __restrict__ R) {
+__global__ void __launch_bounds__(256) k_residual(ProbDev p, const double* __restrict__ Fi,
+                                                  const double* __restrict__ U, double* __restrict__ R) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6) + 1;
   const int l = blockIdx.z % p.nz + 1, r = blockIdx.z / p.nz;
   if (i > p.nx || j > p.ny) return;
-  const double F = assembled_rhs(p, r, i, j, l);  // lifted for l = 1, nz
+  const long long idx = r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+  const double F = Fi[idx];
   const double* Ur = U + r * p.u_stride;
   double acc = 0.0;
   for (int o = -1; o <= 1; ++o) {
@@ -393,7 +614,7 @@ __global__ void __launch_bounds__(256) k_residual(ProbDev p, const double* __res
     }
     acc += s;
   }
-  R[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] = F - acc;
+  R[idx] = F - acc;
 }
 
 __global__ void k_stats_reset(unsigned long long* s) {

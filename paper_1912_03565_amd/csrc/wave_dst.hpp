@@ -1,4 +1,4 @@
-// wave_dst.hpp - DST-I of one grid line per wavefront (CDNA4, wave64).
+// wave_dst.hpp - DST-I of one grid line per group of wavefronts (CDNA4, wave64).
 //
 // The 2-D sine transform of Section 3.6 is applied as 1-D DST-I sums along x
 // and along y:  S_k = sum_{n=1}^{N} x_n sin(pi k n / M),  M = N + 1.
@@ -9,15 +9,25 @@
 // Splitting the length-2M DFT of the odd extension of x into even and odd
 // frequencies shows that the M-point DFT W of w carries the whole transform:
 //     S_{2q} = -Im(W_q)/2,   S_{2q+1} = Re(W_q)/2,   q = 0..M/2-1.
-// W is computed by a Stockham radix-4/8/16 FFT.  The line is spread over L lanes
-// with R = M/L complex values per lane; element e lives in lane e mod L, slot
-// e div L, both on input and on output, so butterflies run in registers and only
-// the L-lane transposes between stages go through a per-wave LDS buffer of M
-// elements (real and imaginary parts exchanged in turn for FP64, which keeps the
-// buffer at M doubles).
+// W is computed by a Stockham FFT of radix 2..16.  A line is spread over L lanes
+// (one or two wavefronts) with R = M/L complex values per lane; element e lives in
+// lane e mod L, slot e div L, on input and on output, so butterflies run in
+// registers and only the transposes between stages go through LDS.
 //
-// Dense path (any N <= 1024).  Each lane sums S_k for its modes k directly,
-// using a table sin(pi r/M), r < 2M.
+// LDS layout: every line buffer is indexed through lp(p) = p + p/16, one pad
+// element per 16, so the stride-16 writes of the Stockham stages and the
+// stride-2 accesses of the DST slots fall in distinct banks.  A buffer holds
+// lp(M) elements; FP64 exchanges move the real and then the imaginary parts
+// through it, FP32 exchanges move complex pairs in one go.
+//
+// Twiddles live in LDS, filled once per workgroup: tab[n] = exp(-i pi n/M), n < M, for
+// the pre-processing, and after it one table per Stockham stage (radix RS, span NSP)
+// laid out [r - 1][jm] = exp(-2 pi i jm r/(NSP RS)), so that the lanes of a wave read
+// consecutive or identical entries (conflict-free) instead of entries a power of two
+// apart.
+//
+// Dense path (any N <= 1024).  Each lane sums S_k for its modes k directly, using a
+// table sin(pi r/M), r < 2M, in global memory.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -40,6 +50,8 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 template <typename T>
 __device__ __forceinline__ cx<T> cmi(cx<T> a) { return {a.im, -a.re}; }
 
+__host__ __device__ constexpr int lp(int p) { return p + (p >> 4); }
+
 // Compiler-level ordering point for LDS traffic inside one wavefront.  LDS
 // instructions of a wave execute in program order, so a wave-private buffer
 // needs no hardware barrier, only that the compiler keeps the order.
@@ -47,6 +59,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ordering point for a line spread over WPL wavefronts of the same workgroup.
+// With WPL > 1 the workgroup must consist of lines that all run the transform.
+template <int WPL>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WPL == 1) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -96,41 +119,33 @@ __device__ __forceinline__ void dft8(cx<T>* a) {
 
 template <typename T>
 __device__ __forceinline__ void dft16(cx<T>* a) {
-  // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
-  cx<T> b[4][4];
+  // 16 = 4 x 4, in place: n = n2 + 4 n1, k = k1 + 4 k2.  Column DFTs over n1 leave
+  // (n2, k1) in a[n2 + 4 k1]; after the twiddles w16^{n2 k1}, row DFTs over n2 leave
+  // X[k1 + 4 k2] in a[4 k1 + k2]; a final register renaming restores natural order.
 #pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) {
-    b[n2][0] = a[n2];
-    b[n2][1] = a[4 + n2];
-    b[n2][2] = a[8 + n2];
-    b[n2][3] = a[12 + n2];
-    dft4(b[n2][0], b[n2][1], b[n2][2], b[n2][3]);  // -> index k1
-  }
-  // twiddles w16^{n2 k1}
+  for (int n2 = 0; n2 < 4; ++n2) dft4(a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]);
   const T c1 = (T)0.92387953251128675612818318939679;  // cos(pi/8)
   const T s1 = (T)0.38268343236508977172845998403040;  // sin(pi/8)
   const T h = (T)0.70710678118654752440084436210485;
-  // n2 = 1: k1 = 1,2,3 -> w^1, w^2, w^3
-  b[1][1] = cmul(b[1][1], cx<T>{c1, -s1});
-  b[1][2] = cmul(b[1][2], cx<T>{h, -h});
-  b[1][3] = cmul(b[1][3], cx<T>{s1, -c1});
-  // n2 = 2: w^2, w^4, w^6
-  b[2][1] = cmul(b[2][1], cx<T>{h, -h});
-  b[2][2] = cmi(b[2][2]);
-  b[2][3] = cmul(b[2][3], cx<T>{-h, -h});
-  // n2 = 3: w^3, w^6, w^9
-  b[3][1] = cmul(b[3][1], cx<T>{s1, -c1});
-  b[3][2] = cmul(b[3][2], cx<T>{-h, -h});
-  b[3][3] = cmul(b[3][3], cx<T>{-c1, s1});
+  a[1 + 4] = cmul(a[1 + 4], cx<T>{c1, -s1});
+  a[1 + 8] = cmul(a[1 + 8], cx<T>{h, -h});
+  a[1 + 12] = cmul(a[1 + 12], cx<T>{s1, -c1});
+  a[2 + 4] = cmul(a[2 + 4], cx<T>{h, -h});
+  a[2 + 8] = cmi(a[2 + 8]);
+  a[2 + 12] = cmul(a[2 + 12], cx<T>{-h, -h});
+  a[3 + 4] = cmul(a[3 + 4], cx<T>{s1, -c1});
+  a[3 + 8] = cmul(a[3 + 8], cx<T>{-h, -h});
+  a[3 + 12] = cmul(a[3 + 12], cx<T>{-c1, s1});
 #pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1) {
-    cx<T> x0 = b[0][k1], x1 = b[1][k1], x2 = b[2][k1], x3 = b[3][k1];
-    dft4(x0, x1, x2, x3);
-    a[k1] = x0;
-    a[k1 + 4] = x1;
-    a[k1 + 8] = x2;
-    a[k1 + 12] = x3;
-  }
+  for (int k1 = 0; k1 < 4; ++k1) dft4(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // a[4 k1 + k2] -> a[k1 + 4 k2]: transpose of the 4 x 4 index grid
+  cx<T> t;
+  t = a[1]; a[1] = a[4]; a[4] = t;
+  t = a[2]; a[2] = a[8]; a[8] = t;
+  t = a[3]; a[3] = a[12]; a[12] = t;
+  t = a[6]; a[6] = a[9]; a[9] = t;
+  t = a[7]; a[7] = a[13]; a[13] = t;
+  t = a[11]; a[11] = a[14]; a[14] = t;
 }
 
 template <typename T, int RS>
@@ -142,28 +157,65 @@ __device__ __forceinline__ void dft(cx<T>* a) {
 }
 
 // ---------------------------------------------------------------------------
-// FFT geometry per line length M.
+// FFT geometry: WPL wavefronts per line (1, or 2 for M >= 512).
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, int WPL>
 struct FftGeom {
   static_assert(M == 64 || M == 128 || M == 256 || M == 512 || M == 1024, "unsupported M");
-  static constexpr int R = (M / 64 < 4) ? 4 : M / 64;  // complex values per lane
-  static constexpr int L = M / R;                       // lanes per line
-  static constexpr int NS = R;                          // output slots per lane
+  static_assert(WPL == 1 || (WPL == 2 && M >= 512), "two waves per line need M >= 512");
+  static constexpr int L = (M >= 256) ? 64 * WPL : M / 4;   // lanes per line
+  static constexpr int R = M / L;                          // complex values per lane
+  static constexpr int NS = R;                             // output slots per lane
 };
 
-// twiddle table: tw[k] = exp(-i pi k / M), k < 2M, stored as (re, im) doubles
-template <typename T>
-__device__ __forceinline__ cx<T> twid(const double2* __restrict__ tw, int k) {
-  double2 t = tw[k];
-  return {(T)t.x, (T)t.y};
+// register arrays of one line: complex values and real output slots per lane
+template <typename T, int M, int WPL>
+using LineRegs = cx<T>[FftGeom<M, WPL>::R];
+template <typename T, int M, int WPL>
+using LineOut = T[FftGeom<M, WPL>::R];
+
+// LDS elements of T in one line buffer
+template <typename T, int M>
+__host__ __device__ constexpr int fft_buf_elems() {
+  return sizeof(T) == 8 ? lp(M) : 2 * lp(M);
 }
 
-// One Stockham stage of radix RS and span NSP on the register layout.
-template <typename T, int M, int RS, int NSP>
-__device__ __forceinline__ void fft_stage(cx<T> (&v)[FftGeom<M>::R], int tl,
-                                          const double2* __restrict__ tw) {
-  constexpr int R = FftGeom<M>::R, L = FftGeom<M>::L, NB = R / RS;
+// LDS complex entries of the twiddle tables of one FFT size
+template <int M>
+__host__ __device__ constexpr int tw_entries() {
+  return 2 * M;
+}
+
+// Fill the stage table of stage (RS, NSP) at stab + OFF from the global table
+// tw[k] = exp(-i pi k/M), k < 2M (every thread of the block takes part).
+template <typename T, int M, int RS, int NSP, int OFF>
+__device__ __forceinline__ void fill_stage(cx<T>* stab, const double2* __restrict__ tw) {
+  constexpr int step = 2 * (M / (NSP * RS));
+  for (int e = threadIdx.x; e < (RS - 1) * NSP; e += blockDim.x) {
+    const int r = 1 + e / NSP, jm = e % NSP;
+    const double2 t = tw[step * jm * r];
+    stab[OFF + e] = {(T)t.x, (T)t.y};
+  }
+}
+
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void fill_stage_tables(cx<T>* stab, const double2* __restrict__ tw);
+
+// Fill tab[0..M) and the stage tables behind it (a barrier must follow before use).
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void load_twiddles(cx<T>* tab, const double2* __restrict__ tw) {
+  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    const double2 t = tw[k];
+    tab[k] = {(T)t.x, (T)t.y};
+  }
+  fill_stage_tables<T, M, WPL>(tab + M, tw);
+}
+
+// One Stockham stage of radix RS and span NSP on the register layout; its twiddles
+// are stab[OFF + (r - 1) NSP + jm].
+template <typename T, int M, int WPL, int RS, int NSP, int OFF>
+__device__ __forceinline__ void fft_stage(LineRegs<T, M, WPL>& v, int tl, const cx<T>* stab) {
+  constexpr int R = FftGeom<M, WPL>::R, L = FftGeom<M, WPL>::L, NB = R / RS;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     cx<T> u[RS];
@@ -171,9 +223,8 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[FftGeom<M>::R], int tl,
     for (int r = 0; r < RS; ++r) u[r] = v[b + r * NB];
     if constexpr (NSP > 1) {
       const int jm = (tl + L * b) & (NSP - 1);
-      constexpr int step = 2 * (M / (NSP * RS));
 #pragma unroll
-      for (int r = 1; r < RS; ++r) u[r] = cmul(u[r], twid<T>(tw, step * jm * r));
+      for (int r = 1; r < RS; ++r) u[r] = cmul(u[r], stab[OFF + (r - 1) * NSP + jm]);
     }
     dft<T, RS>(u);
 #pragma unroll
@@ -181,110 +232,173 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[FftGeom<M>::R], int tl,
   }
 }
 
-// Transpose between stage (RS, NSP) and a following stage of radix RS2 through LDS.
-template <typename T, int M, int RS, int NSP, int RS2>
-__device__ __forceinline__ void fft_exchange(cx<T> (&v)[FftGeom<M>::R], T* buf, int tl) {
-  constexpr int R = FftGeom<M>::R, L = FftGeom<M>::L, NB = R / RS, NB2 = R / RS2;
-  int opos[R], ipos[R];
-#pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int j = tl + L * b;
-      opos[b + r * NB] = (j / NSP) * NSP * RS + (j & (NSP - 1)) + r * NSP;
-    }
-#pragma unroll
-  for (int b = 0; b < NB2; ++b)
-#pragma unroll
-    for (int r = 0; r < RS2; ++r) ipos[b + r * NB2] = tl + L * b + r * (M / RS2);
+// LDS positions of the transpose between stage (RS, NSP) and a following stage of
+// radix RS2 (recomputed where used, so they do not occupy registers)
+template <int M, int WPL, int RS, int NSP>
+__device__ __forceinline__ int fft_opos(int tl, int s) {
+  constexpr int L = FftGeom<M, WPL>::L, NB = FftGeom<M, WPL>::R / RS;
+  const int b = s % NB, r = s / NB;
+  const int j = tl + L * b;
+  return lp((j / NSP) * NSP * RS + (j & (NSP - 1)) + r * NSP);
+}
+
+template <int M, int WPL, int RS2>
+__device__ __forceinline__ int fft_ipos(int tl, int s) {
+  constexpr int L = FftGeom<M, WPL>::L, NB2 = FftGeom<M, WPL>::R / RS2;
+  const int b = s % NB2, r = s / NB2;
+  return lp(tl + L * b + r * (M / RS2));
+}
+
+template <typename T, int M, int WPL, int RS, int NSP, int RS2>
+__device__ __forceinline__ void fft_exchange(LineRegs<T, M, WPL>& v, T* buf, int tl) {
+  constexpr int R = FftGeom<M, WPL>::R;
   if constexpr (sizeof(T) == 4) {
     cx<T>* cb = reinterpret_cast<cx<T>*>(buf);
 #pragma unroll
-    for (int s = 0; s < R; ++s) cb[opos[s]] = v[s];
-    wave_sync();
+    for (int s = 0; s < R; ++s) cb[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s];
+    line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s] = cb[ipos[s]];
-    wave_sync();
+    for (int s = 0; s < R; ++s) v[s] = cb[fft_ipos<M, WPL, RS2>(tl, s)];
+    line_sync<WPL>();
   } else {
 #pragma unroll
-    for (int s = 0; s < R; ++s) buf[opos[s]] = v[s].re;
-    wave_sync();
+    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s].re;
+    line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s].re = buf[ipos[s]];
-    wave_sync();
+    for (int s = 0; s < R; ++s) v[s].re = buf[fft_ipos<M, WPL, RS2>(tl, s)];
+    line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) buf[opos[s]] = v[s].im;
-    wave_sync();
+    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s].im;
+    line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s].im = buf[ipos[s]];
-    wave_sync();
+    for (int s = 0; s < R; ++s) v[s].im = buf[fft_ipos<M, WPL, RS2>(tl, s)];
+    line_sync<WPL>();
   }
 }
 
-template <typename T, int M>
-__device__ __forceinline__ void fft_run(cx<T> (&v)[FftGeom<M>::R], T* buf, int tl,
-                                        const double2* __restrict__ tw) {
-  if constexpr (M == 64) {
-    fft_stage<T, M, 4, 1>(v, tl, tw);
-    fft_exchange<T, M, 4, 1, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 4>(v, tl, tw);
-    fft_exchange<T, M, 4, 4, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 16>(v, tl, tw);
-  } else if constexpr (M == 128) {
-    fft_stage<T, M, 4, 1>(v, tl, tw);
-    fft_exchange<T, M, 4, 1, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 4>(v, tl, tw);
-    fft_exchange<T, M, 4, 4, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 16>(v, tl, tw);
-    fft_exchange<T, M, 4, 16, 2>(v, buf, tl);
-    fft_stage<T, M, 2, 64>(v, tl, tw);
-  } else if constexpr (M == 256) {
-    fft_stage<T, M, 4, 1>(v, tl, tw);
-    fft_exchange<T, M, 4, 1, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 4>(v, tl, tw);
-    fft_exchange<T, M, 4, 4, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 16>(v, tl, tw);
-    fft_exchange<T, M, 4, 16, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 64>(v, tl, tw);
-  } else if constexpr (M == 512) {
-    fft_stage<T, M, 8, 1>(v, tl, tw);
-    fft_exchange<T, M, 8, 1, 8>(v, buf, tl);
-    fft_stage<T, M, 8, 8>(v, tl, tw);
-    fft_exchange<T, M, 8, 8, 8>(v, buf, tl);
-    fft_stage<T, M, 8, 64>(v, tl, tw);
+// Stage plans: (radix, span, offset of the stage's twiddle table).  Offsets
+// accumulate (RS - 1) NSP entries per stage; every plan uses fewer than M entries.
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void fill_stage_tables(cx<T>* st, const double2* __restrict__ tw) {
+  constexpr int R = FftGeom<M, WPL>::R;
+  if constexpr (R == 4 && M == 64) {
+    fill_stage<T, M, 4, 4, 0>(st, tw);
+    fill_stage<T, M, 4, 16, 12>(st, tw);
+  } else if constexpr (R == 4 && M == 128) {
+    fill_stage<T, M, 4, 4, 0>(st, tw);
+    fill_stage<T, M, 4, 16, 12>(st, tw);
+    fill_stage<T, M, 2, 64, 60>(st, tw);
+  } else if constexpr (R == 4 && M == 256) {
+    fill_stage<T, M, 4, 4, 0>(st, tw);
+    fill_stage<T, M, 4, 16, 12>(st, tw);
+    fill_stage<T, M, 4, 64, 60>(st, tw);
+  } else if constexpr (R == 4 && M == 512) {
+    fill_stage<T, M, 4, 4, 0>(st, tw);
+    fill_stage<T, M, 4, 16, 12>(st, tw);
+    fill_stage<T, M, 4, 64, 60>(st, tw);
+    fill_stage<T, M, 2, 256, 252>(st, tw);
+  } else if constexpr (R == 8 && M == 512) {
+    fill_stage<T, M, 8, 8, 0>(st, tw);
+    fill_stage<T, M, 8, 64, 56>(st, tw);
+  } else if constexpr (R == 8 && M == 1024) {
+    fill_stage<T, M, 8, 8, 0>(st, tw);
+    fill_stage<T, M, 8, 64, 56>(st, tw);
+    fill_stage<T, M, 2, 512, 504>(st, tw);
   } else {
-    fft_stage<T, M, 16, 1>(v, tl, tw);
-    fft_exchange<T, M, 16, 1, 16>(v, buf, tl);
-    fft_stage<T, M, 16, 16>(v, tl, tw);
-    fft_exchange<T, M, 16, 16, 4>(v, buf, tl);
-    fft_stage<T, M, 4, 256>(v, tl, tw);
+    static_assert(R == 16 && M == 1024, "no stage plan");
+    fill_stage<T, M, 16, 16, 0>(st, tw);
+    fill_stage<T, M, 4, 256, 240>(st, tw);
   }
 }
 
-// DST-I of the line held in buf[1..M-1] (buf[0] is ignored).  On return, lane
-// lane < L holds out[s] = S_m for m = fft_mode<M>(lane, s); buf is clobbered.
-template <typename T, int M>
-__device__ __forceinline__ void dst_fft(T* buf, T (&out)[FftGeom<M>::R], int lane,
-                                        const double2* __restrict__ tw) {
-  constexpr int R = FftGeom<M>::R, L = FftGeom<M>::L;
-  cx<T> v[R];
-  if (lane < L) {
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, const cx<T>* st) {
+  constexpr int R = FftGeom<M, WPL>::R;
+  if constexpr (R == 4 && M == 64) {
+    fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
+  } else if constexpr (R == 4 && M == 128) {
+    fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 16, 2>(v, buf, tl);
+    fft_stage<T, M, WPL, 2, 64, 60>(v, tl, st);
+  } else if constexpr (R == 4 && M == 256) {
+    fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 16, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 64, 60>(v, tl, st);
+  } else if constexpr (R == 4 && M == 512) {
+    fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 16, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 64, 60>(v, tl, st);
+    fft_exchange<T, M, WPL, 4, 64, 2>(v, buf, tl);
+    fft_stage<T, M, WPL, 2, 256, 252>(v, tl, st);
+  } else if constexpr (R == 8 && M == 512) {
+    fft_stage<T, M, WPL, 8, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 8, 1, 8>(v, buf, tl);
+    fft_stage<T, M, WPL, 8, 8, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 8, 8, 8>(v, buf, tl);
+    fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
+  } else if constexpr (R == 8 && M == 1024) {
+    fft_stage<T, M, WPL, 8, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 8, 1, 8>(v, buf, tl);
+    fft_stage<T, M, WPL, 8, 8, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 8, 8, 8>(v, buf, tl);
+    fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
+    fft_exchange<T, M, WPL, 8, 64, 2>(v, buf, tl);
+    fft_stage<T, M, WPL, 2, 512, 504>(v, tl, st);
+  } else {
+    static_assert(R == 16 && M == 1024, "no stage plan");
+    fft_stage<T, M, WPL, 16, 1, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 16, 1, 16>(v, buf, tl);
+    fft_stage<T, M, WPL, 16, 16, 0>(v, tl, st);
+    fft_exchange<T, M, WPL, 16, 16, 4>(v, buf, tl);
+    fft_stage<T, M, WPL, 4, 256, 240>(v, tl, st);
+  }
+}
+
+// DST-I of the line held in buf[lp(1..M-1)] (entry lp(0) is ignored).  tl is the
+// lane index within the line (0 <= tl < 64 WPL).  On return, lane tl < L holds
+// out[s] = S_m for m = fft_mode<M, WPL>(tl, s); buf is clobbered.  All lanes of the
+// line's waves must call it (lanes tl >= L only take part in the syncs).
+template <typename T, int M, int WPL>
+__device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl, const cx<T>* tab) {
+  constexpr int R = FftGeom<M, WPL>::R, L = FftGeom<M, WPL>::L;
+  LineRegs<T, M, WPL> v;
+  if (tl < L) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int n = lane + L * s;
+      const int n = tl + L * s;
       if (n == 0) {
         v[s] = {(T)0, (T)0};
       } else {
-        const T a = buf[n], b = buf[M - n];
+        const T a = buf[lp(n)], b = buf[lp(M - n)];
         const T u = a - b, z = a + b;
-        const cx<T> t = twid<T>(tw, n);  // (cos, -sin)(pi n/M)
+        const cx<T> t = tab[n];  // (cos, -sin)(pi n/M)
         v[s] = {u - z * t.im, z * t.re};
       }
     }
   }
-  wave_sync();
-  if (lane < L) {
-    fft_run<T, M>(v, buf, lane, tw);
+  line_sync<WPL>();
+  if (tl < L) {
+    fft_run<T, M, WPL>(v, buf, tl, tab + M);
+  } else if constexpr (WPL > 1) {
+    static_assert(WPL == 1 || L == 64 * WPL, "all lanes of a multi-wave line are active");
+  }
+  if (tl < L) {
 #pragma unroll
     for (int s = 0; s < R / 2; ++s) {
       out[2 * s] = (T)-0.5 * v[s].im;
@@ -293,17 +407,17 @@ __device__ __forceinline__ void dst_fft(T* buf, T (&out)[FftGeom<M>::R], int lan
   }
 }
 
-template <int M>
-__device__ __forceinline__ int fft_mode(int lane, int s) {
-  constexpr int L = FftGeom<M>::L;
-  if (lane >= L) return -1;
-  const int m = 2 * (lane + L * (s >> 1)) + (s & 1);
+template <int M, int WPL>
+__device__ __forceinline__ int fft_mode(int tl, int s) {
+  constexpr int L = FftGeom<M, WPL>::L;
+  if (tl >= L) return -1;
+  const int m = 2 * (tl + L * (s >> 1)) + (s & 1);
   return (m >= 1 && m <= M - 1) ? m : -1;
 }
 
 // ---------------------------------------------------------------------------
-// Dense path: any N <= 1024.  out[s] = S_k, k = 1 + lane + 64 s.
-// sintab[r] = sin(pi r/M), r < 2M.
+// Dense path: any N <= 1024, one wave per line.  out[s] = S_k, k = 1 + lane + 64 s.
+// sintab[r] = sin(pi r/M), r < 2M.  The line is read from buf[lp(n)].
 // ---------------------------------------------------------------------------
 constexpr int kDenseSlots = 16;
 
@@ -320,7 +434,7 @@ __device__ __forceinline__ void dst_dense(const T* buf, int N, T (&out)[kDenseSl
       for (int n = 1; n <= N; ++n) {
         idx += k;
         if (idx >= twoM) idx -= twoM;
-        acc += buf[n] * (T)sintab[idx];
+        acc += buf[lp(n)] * (T)sintab[idx];
       }
     }
     out[s] = acc;

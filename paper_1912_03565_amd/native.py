@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcs3d.so")
+# CS3D_LIBRARY selects another build of the same library (e.g. an autotuned or
+# instrumented one); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("CS3D_LIBRARY") or os.path.join(HERE, "libcs3d.so")
 
 OK = 0
 E_INVAL = 1
