@@ -443,7 +443,7 @@ static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStr
   const int nzc = (p->d.nz + kZChunk - 1) / kZChunk;
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, s, pd);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreads), 0, s, pd);
   return hipGetLastError();
 }
 

@@ -76,13 +76,14 @@ struct Tx<0, WPL> {
 template <typename T, int M, int WPL>
 using TxOut = T[Tx<M, WPL>::NS];
 
-template <typename T, int M, int WPL>
+template <typename T, int M, int WPL, bool BLOCK_SYNC = false>
 __device__ __forceinline__ void line_dst(T* buf, int N, TxOut<T, M, WPL>& out, int tl, const cx<T>* tab,
-                                         const double* sintab) {
+                                         const double* sintab, const T* src = nullptr) {
   if constexpr (M == 0) {
-    dst_dense<T>(buf, N, out, tl, sintab);
+    dst_dense<T>(buf, N, out, tl, sintab, src);
+    if constexpr (BLOCK_SYNC) __syncthreads();
   } else {
-    dst_fft<T, M, WPL>(buf, out, tl, tab);
+    dst_fft<T, M, WPL, BLOCK_SYNC>(buf, out, tl, tab, src);
   }
 }
 
@@ -111,8 +112,8 @@ __host__ __device__ constexpr int tw_bytes() {
 __host__ __device__ constexpr int tile_stride(int nx) { return (nx & 1) ? nx + 2 : nx + 1; }
 
 // ---------------------------------------------------------------------------
-// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 256 threads
-// (64 x 4, four y-rows each), marching over kZChunk planes.
+// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 512 threads
+// (64 x 8, two y-rows each), marching over kZChunk planes with two planes in flight.
 // ---------------------------------------------------------------------------
 constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;
 constexpr int kSX = kRX + 2 * kRH, kSY = kRY + 2 * kRH;
@@ -133,9 +134,11 @@ __device__ __forceinline__ double plane9(const double* __restrict__ w, const dou
          w[2] * (c[-sy] + c[sy]) + w[3] * c[0];
 }
 
-constexpr int kRLoads = (kSY * kSX + 255) / 256;  // plane-tile elements per thread
+constexpr int kRThreads = 512;
+constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread
+constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
-__global__ void __launch_bounds__(256) k_rhs(ProbDev p) {
+__global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
   __shared__ double win[5][kSY * kSX];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
@@ -152,38 +155,37 @@ __global__ void __launch_bounds__(256) k_rhs(ProbDev p) {
   bool ok[kRLoads];
 #pragma unroll
   for (int k = 0; k < kRLoads; ++k) {
-    const int e = threadIdx.x + 256 * k;
+    const int e = threadIdx.x + kRThreads * k;
     const int yy = e / kSX, xx = e - yy * kSX;
     const int gx = x0 - kRH + xx, gy = y0 - kRH + yy;
     ok[k] = e < kSY * kSX && gx >= 0 && gx <= p.nx + 1 && gy >= 0 && gy <= p.ny + 1;
     off[k] = ok[k] ? gx + sy * gy : 0;
   }
-  double pre[kRLoads];
-  auto fetch = [&](int q) {
+  // two planes in flight in registers
+  double pa[kRLoads], pb[kRLoads];
+  auto fetch = [&](double(&pre)[kRLoads], int q) {
     const bool qok = q >= 0 && q <= p.nz + 1;
 #pragma unroll
     for (int k = 0; k < kRLoads; ++k) pre[k] = (qok && ok[k]) ? f[off[k] + sz * q] : 0.0;
   };
-  auto stash = [&](int q) {
+  auto stash = [&](const double(&pre)[kRLoads], int q) {
     double* w = win[(q + 5) % 5];
 #pragma unroll
     for (int k = 0; k < kRLoads; ++k) {
-      const int e = threadIdx.x + 256 * k;
+      const int e = threadIdx.x + kRThreads * k;
       if (e < kSY * kSX) w[e] = pre[k];
     }
   };
   for (int q = lb - halo; q < lb + halo; ++q) {
-    fetch(q);
-    stash(q);
+    fetch(pa, q);
+    stash(pa, q);
   }
-  fetch(lb + halo);
+  fetch(pa, lb + halo);
+  fetch(pb, lb + halo + 1);
 
   const int i = x0 + tx;
   const double hz2 = p.hz * p.hz;
-  for (int l = lb; l <= le; ++l) {
-    stash(l + halo);
-    __syncthreads();
-    if (l < le) fetch(l + halo + 1);  // in flight while this plane is computed
+  auto compute = [&](int l) {
     const double* P0 = win[(l + 5) % 5];
     const double* Pm = win[(l + 4) % 5];
     const double* Pp = win[(l + 6) % 5];
@@ -191,8 +193,8 @@ __global__ void __launch_bounds__(256) k_rhs(ProbDev p) {
     const double* Ppp = win[(l + 7) % 5];
     const double kl = p.k2[l], kzl = p.k2z[l];
 #pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-      const int yl = ty * 4 + k, j = y0 + yl;
+    for (int k = 0; k < kRRows; ++k) {
+      const int yl = ty * kRRows + k, j = y0 + yl;
       if (i > p.nx || j > p.ny) continue;
       const int c0 = (yl + kRH) * kSX + tx + kRH;  // tile index of (i, j)
       const double f0 = P0[c0];
@@ -239,7 +241,20 @@ __global__ void __launch_bounds__(256) k_rhs(ProbDev p) {
       if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
       p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] = F;
     }
+  };
+  for (int l = lb; l <= le; l += 2) {
+    stash(pa, l + halo);
     __syncthreads();
+    if (l + 2 <= le) fetch(pa, l + halo + 2);
+    compute(l);
+    __syncthreads();
+    if (l + 1 <= le) {
+      stash(pb, l + 1 + halo);
+      __syncthreads();
+      if (l + 3 <= le) fetch(pb, l + halo + 3);
+      compute(l + 1);
+      __syncthreads();
+    }
   }
 }
 
@@ -516,6 +531,12 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
 // Persistent like K1: the next tile's y-line segments are loaded into registers
 // while the current tile is transformed.
 // ---------------------------------------------------------------------------
+#ifndef CS3D_INV_PREFETCH
+#define CS3D_INV_PREFETCH 0
+#endif
+// K4 register prefetch of the next tile (off by default: it costs spills at M = 1024)
+constexpr bool kInvPrefetch = CS3D_INV_PREFETCH != 0;
+
 template <typename T, int MX>
 __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
@@ -541,9 +562,10 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
     }
   };
   int t = blockIdx.x;
-  if (t < ntiles) fetch(t);
+  if (kInvPrefetch && t < ntiles) fetch(t);
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
+    if (!kInvPrefetch) fetch(t);
     __syncthreads();  // the previous transform is done with the LDS
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -551,27 +573,13 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
       const int n0 = idx / kTileJ, jj = idx % kTileJ;
       if (n0 < p.nx) smem[jj * ts + n0 + 1] = pre[k];
     }
-    __syncthreads();
-    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
-    T col[kNV];
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) {
-      const int n = 1 + lane + 64 * k;
-      col[k] = (x.active && n <= p.nx) ? smem[w * ts + n] : (T)0;
-    }
-    __syncthreads();
+    __syncthreads();  // also publishes the twiddle table on the first pass
+    if (kInvPrefetch && t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
+    // the transform reads its input straight from tile row w; the workgroup barrier
+    // inside separates those reads from the exchanges that overlay the tile
+    T out[NS];
+    line_dst<T, MX, 1, true>(buf, p.nx, out, lane, tab, p.sinx, smem + w * ts);
     if (x.active) {
-#pragma unroll
-      for (int k = 0; k < kNV; ++k) {
-        const int n = 1 + lane + 64 * k;
-        if (n <= p.nx) buf[lp(n)] = col[k];
-      }
-      if (lane == 0) buf[lp(0)] = (T)0;
-    }
-    wave_sync();
-    if (x.active) {
-      T out[NS];
-      line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
       double* u = p.u + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
 #pragma unroll
       for (int s = 0; s < NS; ++s) {

@@ -370,12 +370,16 @@ __device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, 
   }
 }
 
-// DST-I of the line held in buf[lp(1..M-1)] (entry lp(0) is ignored).  tl is the
-// lane index within the line (0 <= tl < 64 WPL).  On return, lane tl < L holds
-// out[s] = S_m for m = fft_mode<M, WPL>(tl, s); buf is clobbered.  All lanes of the
-// line's waves must call it (lanes tl >= L only take part in the syncs).
-template <typename T, int M, int WPL>
-__device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl, const cx<T>* tab) {
+// DST-I of a line.  The input x_n (1 <= n < M) is read from src[n] (unpadded; src
+// may alias nothing the exchanges write before the first sync) or, when src is
+// null, from buf[lp(n)].  BLOCK_SYNC makes the sync after the input has been read a
+// workgroup barrier, for callers whose line buffers overlay a shared input tile.
+// tl is the lane index within the line (0 <= tl < 64 WPL).  On return, lane tl < L
+// holds out[s] = S_m for m = fft_mode<M, WPL>(tl, s); buf is clobbered.  All lanes
+// of the line's waves must call it (lanes tl >= L only take part in the syncs).
+template <typename T, int M, int WPL, bool BLOCK_SYNC = false>
+__device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl, const cx<T>* tab,
+                                        const T* src = nullptr) {
   constexpr int R = FftGeom<M, WPL>::R, L = FftGeom<M, WPL>::L;
   LineRegs<T, M, WPL> v;
   if (tl < L) {
@@ -385,20 +389,21 @@ __device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl,
       if (n == 0) {
         v[s] = {(T)0, (T)0};
       } else {
-        const T a = buf[lp(n)], b = buf[lp(M - n)];
+        const T a = src ? src[n] : buf[lp(n)];
+        const T b = src ? src[M - n] : buf[lp(M - n)];
         const T u = a - b, z = a + b;
         const cx<T> t = tab[n];  // (cos, -sin)(pi n/M)
         v[s] = {u - z * t.im, z * t.re};
       }
     }
   }
-  line_sync<WPL>();
-  if (tl < L) {
-    fft_run<T, M, WPL>(v, buf, tl, tab + M);
-  } else if constexpr (WPL > 1) {
-    static_assert(WPL == 1 || L == 64 * WPL, "all lanes of a multi-wave line are active");
+  if constexpr (BLOCK_SYNC) {
+    __syncthreads();
+  } else {
+    line_sync<WPL>();
   }
   if (tl < L) {
+    fft_run<T, M, WPL>(v, buf, tl, tab + M);
 #pragma unroll
     for (int s = 0; s < R / 2; ++s) {
       out[2 * s] = (T)-0.5 * v[s].im;
@@ -423,7 +428,7 @@ constexpr int kDenseSlots = 16;
 
 template <typename T>
 __device__ __forceinline__ void dst_dense(const T* buf, int N, T (&out)[kDenseSlots], int lane,
-                                          const double* __restrict__ sintab) {
+                                          const double* __restrict__ sintab, const T* src = nullptr) {
   const int twoM = 2 * (N + 1);
 #pragma unroll
   for (int s = 0; s < kDenseSlots; ++s) {
@@ -434,7 +439,7 @@ __device__ __forceinline__ void dst_dense(const T* buf, int N, T (&out)[kDenseSl
       for (int n = 1; n <= N; ++n) {
         idx += k;
         if (idx >= twoM) idx -= twoM;
-        acc += buf[lp(n)] * (T)sintab[idx];
+        acc += (src ? src[n] : buf[lp(n)]) * (T)sintab[idx];
       }
     }
     out[s] = acc;
