@@ -9,8 +9,10 @@ Inputs are generated on the device before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  value = right-hand sides x N^3 unknowns per second of wall time
-(HIP events around the K steps).
+Both the FP64 path and the mixed path (FP32 transforms, FP64 tridiagonal solves, two
+FP64-residual refinement steps) are timed; value = right-hand sides x N^3 unknowns per
+second of the faster path whose solution differs from the FP64 one by at most 1e-10
+(relative 2-norm), HIP events around the K steps.
 """
 import argparse
 import json
@@ -51,7 +53,8 @@ def stage_bytes(nx, ny, nz, nrhs, elem=8):
 
 
 STAGE_NAMES = ["k_rhs (RHS operator + lift)", "k_fwd_x (x-DST)", "k_fwd_y (y-DST + forward elimination)",
-               "k_back_y (back substitution + inverse y-DST)", "k_inv_x (inverse x-DST)"]
+               "k_back_y (back substitution + inverse y-DST)", "k_inv_x (inverse x-DST)",
+               "k_residual + k_sumsq (FP64 residual)"]
 
 
 def cpu_baseline(p_dev, planes):
@@ -93,6 +96,34 @@ def cpu_baseline(p_dev, planes):
                       f"columns; {t:.1f} s on {threads} host threads"}
 
 
+def time_path(cs3d, p, nrhs, precision, steps, warmup, dev):
+    """Warm up, then time `steps` solves with HIP events; returns (u, ms per step, stats)."""
+    import torch
+
+    plan = cs3d.plan_for_problem(p, precision=precision, refine_steps=2, max_rhs=nrhs, device=dev)
+    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
+    log(f"[bench] {precision}: plan ready, workspace {plan.ws_bytes / 2**30:.2f} GiB; warmup {warmup}")
+    for _ in range(warmup):
+        plan.solve(p.f, out=u)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(p.f, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = plan.stats()
+    log(f"[bench] {precision}: {ms:.3f} ms/step; stages {['%.3f' % x for x in st['stage_ms']]}")
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+    return u, ms, st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +133,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--cpu-planes", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="after the timed steps, copy 2 GiB once with a plain device copy "
                          "(the reference for scaling HBM byte counters)")
@@ -120,38 +152,48 @@ def main():
     log(f"[bench] generating inputs {n}^3 x {nrhs} on {dev}")
     p = WL.config5(n=n, nrhs=nrhs, device=dev)
     torch.cuda.synchronize()
-    plan = cs3d.plan_for_problem(p, max_rhs=nrhs, device=dev)
-    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
-    log(f"[bench] plan ready, workspace {plan.ws_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        plan.solve(p.f, out=u)
-    torch.cuda.synchronize()
-    plan.reset_timers()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.solve(p.f, out=u)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    st = plan.stats()
-    log(f"[bench] {ms:.3f} ms/step; stages {['%.3f' % s for s in st['stage_ms']]}")
     unknowns = nrhs * n ** 3
-    value = unknowns / (ms / 1e3)
 
-    sb = stage_bytes(n, n, n, nrhs)
-    k = max(range(len(st["stage_ms"])), key=lambda i: st["stage_ms"][i])
-    achieved = sb[k] / (st["stage_ms"][k] / 1e3) / 1e9
+    u64, ms64, st64 = time_path(cs3d, p, nrhs, "fp64", args.steps, args.warmup, dev)
+    paths = {"fp64": {"ms_per_step": round(ms64, 4), "value": round(unknowns / (ms64 / 1e3), 1),
+                      "stage_ms": [round(x, 4) for x in st64["stage_ms"]],
+                      "min_abs_pivot": st64["min_abs_pivot"]}}
+    best = ("fp64", ms64, st64)
+    if not args.no_mixed:
+        umx, msmx, stmx = time_path(cs3d, p, nrhs, "mixed", args.steps, args.warmup, dev)
+        diff = [float(torch.linalg.vector_norm(umx[r] - u64[r]) / torch.linalg.vector_norm(u64[r]))
+                for r in range(nrhs)]
+        del umx
+        torch.cuda.empty_cache()
+        ok = max(diff) <= 1e-10 and stmx["status"] == 0
+        paths["mixed"] = {"ms_per_step": round(msmx, 4), "value": round(unknowns / (msmx / 1e3), 1),
+                          "stage_ms": [round(x, 4) for x in stmx["stage_ms"]],
+                          "refine_steps": stmx["refine_done"],
+                          "residual_history": [x for x in stmx["residual_history"][: stmx["refine_done"] + 1]],
+                          "rel_err_vs_fp64_gpu": max(diff), "meets_1e-10": ok,
+                          "speedup_vs_fp64": round(ms64 / msmx, 4)}
+        log(f"[bench] mixed: rel diff vs fp64 {max(diff):.3e}, residuals {paths['mixed']['residual_history']}")
+        if ok and msmx < ms64:
+            best = ("mixed", msmx, stmx)
+    del u64
+    torch.cuda.empty_cache()
+
+    name, ms, st = best
+    value = unknowns / (ms / 1e3)
+    elem = 8 if name == "fp64" else 4
+    sb = stage_bytes(n, n, n, nrhs, elem)
+    stage_ms = st["stage_ms"][: len(sb)]
+    k = max(range(len(sb)), key=lambda i: stage_ms[i])
+    achieved = sb[k] / (stage_ms[k] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": STAGE_NAMES[k], "kernel_ms": round(st["stage_ms"][k], 4),
-                "algorithmic_bytes": sb[k]}
-    stages = [{"kernel": STAGE_NAMES[i], "ms": round(st["stage_ms"][i], 4),
-               "algorithmic_GBs": round(sb[i] / (st["stage_ms"][i] / 1e3) / 1e9, 1)}
-              for i in range(len(st["stage_ms"]))]
-    whole_gbs = sum(sb) / (ms / 1e3) / 1e9
+                "kernel": STAGE_NAMES[k], "kernel_ms": round(stage_ms[k], 4), "algorithmic_bytes": sb[k]}
+    if name == "mixed":
+        roofline["note"] = "per-launch bytes of one transform pass; the mixed path runs 3 per solve"
+    stages = [{"kernel": STAGE_NAMES[i], "ms": round(stage_ms[i], 4),
+               "algorithmic_GBs": round(sb[i] / (stage_ms[i] / 1e3) / 1e9, 1) if stage_ms[i] > 0 else None}
+              for i in range(len(sb))]
+    whole_gbs = sum(sb) / (ms64 / 1e3) / 1e9
 
     if args.traffic_probe:
         src = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
@@ -165,7 +207,6 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_planes} planes")
-        del u
         cpu = cpu_baseline(p, args.cpu_planes)
         cpu["value"] = round(cpu["value"], 1)
         log(f"[bench] cpu baseline {cpu['value']:.3e} unknowns/s")
@@ -173,16 +214,17 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "unknowns/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if name == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"helm6_kexp_{n}^3_x{nrhs}rhs", "grid": [n, n, n], "nrhs": nrhs,
                    "scheme": "6th-order compact Helmholtz", "k": "80 exp(-z)",
                    "rhs": "f*(sin pi x sin 2pi y sin 3pi z) + U[-1,1] noise, seeds 105000+r",
-                   "precision": "fp64"},
+                   "path": name},
         "roofline": roofline,
         "stages": stages,
-        "path_algorithmic_GBs": round(whole_gbs, 1),
-        "min_abs_pivot": st["min_abs_pivot"],
+        "paths": paths,
+        "fp64_path_algorithmic_GBs": round(whole_gbs, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

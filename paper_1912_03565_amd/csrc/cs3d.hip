@@ -21,8 +21,11 @@ using namespace cs3d;
 namespace {
 
 constexpr int kMaxN = 1023;
-constexpr int kRing = 128;      // solves kept for the per-pass timing average
-constexpr int kMaxStages = 8;
+constexpr int kRing = 16;       // solves kept for the per-pass timing average
+constexpr int kMaxMarks = 64;   // timed intervals per solve
+constexpr int kStages = 6;      // stage ids: RHS, x-DST, y fwd, y back, inverse x, residual
+// relative FP64 residual a mixed solve must reach after its refinement steps
+constexpr double kResidualTarget = 1e-12;
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -58,10 +61,14 @@ struct cs3d_plan_s {
   hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
-  // per-pass timing ring: kRing solves x (kMaxStages + 1) events
+  // per-pass timing ring: kRing solves x (kMaxMarks + 1) events; interval k of a solve
+  // belongs to stage ring_sid[...]
   std::vector<hipEvent_t> ring;
+  std::vector<signed char> ring_sid;
+  std::vector<int> ring_n;
   long long solves = 0;   // solves recorded since the last reset
-  int nstages = 0;
+  int cur_marks = 0;
+  int refine_done = 0;
   std::vector<double> hW;  // host copy of the weights
 };
 
@@ -282,7 +289,7 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   CS3D_TRY(dalloc(&p->dtwy, twy.size()));
   CS3D_TRY(dalloc(&p->dsinx, sx.size()));
   CS3D_TRY(dalloc(&p->dsiny, sy.size()));
-  CS3D_TRY(dalloc(&p->dstats, 2));
+  CS3D_TRY(dalloc(&p->dstats, kStatsWords));
   CS3D_TRY(hipMemcpyAsync(p->dW, p->hW.data(), p->hW.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipMemcpyAsync(p->dLC, lc.data(), lc.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipMemcpyAsync(p->dk2, k2.data(), k2.size() * 8, hipMemcpyHostToDevice, s));
@@ -295,7 +302,9 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   CS3D_TRY(hipMemcpyAsync(p->dsiny, sy.data(), sy.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipEventCreate(&p->ev0));
   CS3D_TRY(hipEventCreate(&p->ev1));
-  p->ring.assign((size_t)kRing * (kMaxStages + 1), nullptr);
+  p->ring.assign((size_t)kRing * (kMaxMarks + 1), nullptr);
+  p->ring_sid.assign((size_t)kRing * kMaxMarks, 0);
+  p->ring_n.assign(kRing, 0);
   for (hipEvent_t& e : p->ring) CS3D_TRY(hipEventCreate(&e));
   k_stats_reset<<<1, 64, 0, s>>>(p->dstats);
   CS3D_TRY(hipGetLastError());
@@ -320,10 +329,18 @@ static size_t g_elems(const cs3d_plan p) { return (size_t)p->d.nz * p->d.nx * p-
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static size_t n3(const cs3d_plan p) { return (size_t)p->d.nx * p->d.ny * p->d.nz; }
+
+// workspace layout: G (transform intermediate, per rhs) | C (c' of the LU, shared by the
+// right-hand sides) | mixed path only: F (FP64 right-hand side, per rhs) | R (FP64 residual)
+static size_t off_C(const cs3d_plan p, int nrhs) { return round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs); }
+static size_t off_F(const cs3d_plan p, int nrhs) { return off_C(p, nrhs) + round256(g_elems(p) * 8); }
+static size_t off_R(const cs3d_plan p, int nrhs) { return off_F(p, nrhs) + round256(n3(p) * 8 * (size_t)nrhs); }
+
 extern "C" size_t cs3d_workspace_bytes(cs3d_plan p, int nrhs) {
   if (!p || nrhs < 1 || nrhs > p->d.max_rhs) return 0;
-  // G (transform intermediate, per rhs) + C (c' of the LU, shared by the right-hand sides)
-  return round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs) + round256(g_elems(p) * 8);
+  if (p->d.precision == CS3D_FP64) return off_F(p, nrhs);
+  return off_R(p, nrhs) + round256(n3(p) * 8 * (size_t)nrhs);
 }
 
 extern "C" cs3d_status cs3d_set_workspace(cs3d_plan p, void* dev, size_t bytes) {
@@ -482,40 +499,53 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.u_stride = (long long)p->d.nx * p->d.ny * p->d.nz;
   pd.G = p->ws;
   pd.G_stride = (long long)g_elems(p);
-  pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) +
-                                           round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs))
-               : nullptr;
+  pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) + off_C(p, nrhs)) : nullptr;
   pd.stats = p->dstats;
   return pd;
 }
 
-// event marking the start of pass k (k = nstages marks the end) of the current solve
-static hipError_t mark(cs3d_plan p, int k, hipStream_t s) {
-  const size_t slot = (size_t)(p->solves % kRing) * (kMaxStages + 1) + k;
-  return hipEventRecord(p->ring[slot], s);
+// Interval timing: mark(stage) starts an interval of that stage, end_solve closes the last.
+static hipError_t mark(cs3d_plan p, int stage, hipStream_t s) {
+  if (p->cur_marks >= kMaxMarks) return hipSuccess;  // further passes are not timed separately
+  const size_t q = (size_t)(p->solves % kRing);
+  p->ring_sid[q * kMaxMarks + p->cur_marks] = (signed char)stage;
+  return hipEventRecord(p->ring[q * (kMaxMarks + 1) + p->cur_marks++], s);
 }
 
-// FP64 path: [K0 RHS] -> K1 -> K2 -> K3 -> K4.  With an assembled F, K0 is skipped.
-template <typename T>
-static hipError_t solve_passes(cs3d_plan p, const ProbDev& pd, int nrhs, bool with_rhs, hipStream_t s) {
-  hipError_t e;
-  int k = 0;
-  p->nstages = with_rhs ? 5 : 4;
-  if ((e = mark(p, k++, s)) != hipSuccess) return e;
-  if (with_rhs) {
-    if ((e = run_rhs(p, pd, nrhs, s)) != hipSuccess) return e;
-    if ((e = mark(p, k++, s)) != hipSuccess) return e;
-  }
-  if ((e = run_x_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, k++, s)) != hipSuccess) return e;
-  if ((e = run_y_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, k++, s)) != hipSuccess) return e;
-  if ((e = run_y_back<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, k++, s)) != hipSuccess) return e;
-  if ((e = run_x_inv<T>(p, pd, nrhs, s)) != hipSuccess) return e;
-  if ((e = mark(p, k++, s)) != hipSuccess) return e;
+static hipError_t end_solve(cs3d_plan p, hipStream_t s) {
+  const size_t q = (size_t)(p->solves % kRing);
+  const hipError_t e = hipEventRecord(p->ring[q * (kMaxMarks + 1) + p->cur_marks], s);
+  p->ring_n[q] = p->cur_marks;
+  p->cur_marks = 0;
   ++p->solves;
-  return hipSuccess;
+  return e;
+}
+
+// K1 -> K2 -> K3 -> K4 on the right-hand side pd.F (a solve with the transform type T)
+template <typename T>
+static hipError_t transform_solve(cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  hipError_t e;
+  if ((e = mark(p, 1, s)) != hipSuccess) return e;
+  if ((e = run_x_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 2, s)) != hipSuccess) return e;
+  if ((e = run_y_fwd<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 3, s)) != hipSuccess) return e;
+  if ((e = run_y_back<T>(p, pd, nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 4, s)) != hipSuccess) return e;
+  return run_x_inv<T>(p, pd, nrhs, s);
+}
+
+static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s);
+
+// r = F - A U and its squared norm into stats word `slot`
+static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, double* R,
+                                int nrhs, int slot, hipStream_t s) {
+  dim3 grid((p->d.nx + 63) / 64, (p->d.ny + 3) / 4, p->d.nz * nrhs);
+  if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, pd, F, U, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return norm_pass(R, (long long)n3(p) * nrhs, reinterpret_cast<double*>(p->dstats) + slot, s);
 }
 
 static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int assembled, const double* glo,
@@ -524,19 +554,60 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
   if (!p->ws || p->ws_bytes < cs3d_workspace_bytes(p, nrhs)) return CS3D_E_WORKSPACE;
-  if (p->d.precision != CS3D_FP64) return CS3D_E_UNSUPPORTED;
   if (assembled && f == u) return CS3D_E_INVAL;  // F must stay intact until K1 has read all of it
   hipStream_t s = (hipStream_t)hip_stream;
   p->last_stream = s;
-  // the interior F lives in u: K0 writes it there, K1 reads it, K4 overwrites it with the solution
-  const ProbDev pd = make_pd(p, assembled ? nullptr : f, glo, ghi, assembled ? f : u, u, nrhs);
+  p->cur_marks = 0;
+  const bool mixed = p->d.precision != CS3D_FP64;
+  char* ws = reinterpret_cast<char*>(p->ws);
+  // where the interior right-hand side lives: the caller's F, or K0's output (u for the
+  // FP64 path, whose K4 overwrites it last; a workspace array for the mixed path, which
+  // needs F again for every residual)
+  double* Fbuf = mixed ? reinterpret_cast<double*>(ws + off_F(p, nrhs)) : u;
+  const double* F = assembled ? f : Fbuf;
+  ProbDev pd = make_pd(p, assembled ? nullptr : f, glo, ghi, F, Fbuf, nrhs);
   if (hipEventRecord(p->ev0, s) != hipSuccess) return CS3D_E_DEVICE;
-  k_stats_reset<<<1, 64, 0, s>>>(p->dstats);
+  hipLaunchKernelGGL(k_stats_reset, dim3(1), dim3(64), 0, s, p->dstats);
   if (hipGetLastError() != hipSuccess) return CS3D_E_DEVICE;
-  if (solve_passes<double>(p, pd, nrhs, !assembled, s) != hipSuccess) return CS3D_E_DEVICE;
+  if (!assembled) {
+    if (mark(p, 0, s) != hipSuccess || run_rhs(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+  }
+  pd.u = u;
+  pd.accumulate = 0;
+  if (!mixed) {
+    if (transform_solve<double>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+    p->refine_done = 0;
+  } else {
+    // FP32 transforms + FP64 tridiagonal solves, then refine_steps corrections
+    // U += A_mixed^{-1} (F - A U) with the FP64 27-point residual (Section 3.1 operator)
+    double* R = reinterpret_cast<double*>(ws + off_R(p, nrhs));
+    if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
+    if (norm_pass(F, (long long)n3(p) * nrhs, reinterpret_cast<double*>(p->dstats) + 2, s) != hipSuccess)
+      return CS3D_E_DEVICE;
+    if (transform_solve<float>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+    for (int it = 0; it <= p->d.refine_steps; ++it) {
+      if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
+      if (residual_pass(p, pd, F, u, R, nrhs, 3 + it, s) != hipSuccess) return CS3D_E_DEVICE;
+      if (it == p->d.refine_steps) break;
+      ProbDev pc = pd;
+      pc.F = R;
+      pc.accumulate = 1;
+      if (transform_solve<float>(p, pc, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+    }
+    p->refine_done = p->d.refine_steps;
+  }
+  if (end_solve(p, s) != hipSuccess) return CS3D_E_DEVICE;
   if (hipEventRecord(p->ev1, s) != hipSuccess) return CS3D_E_DEVICE;
   p->timed = true;
   return CS3D_OK;
+}
+
+static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)blocks), dim3(256), 0, s, x, n, acc);
+  return hipGetLastError();
 }
 
 extern "C" cs3d_status cs3d_solve(cs3d_plan p, int nrhs, const double* dev_f, const double* dev_g_lo,
@@ -573,25 +644,34 @@ extern "C" cs3d_status cs3d_get_stats(cs3d_plan p, cs3d_stats* out) {
   for (double& v : out->residual_history) v = NAN;
   if (p->last_stream && hipStreamSynchronize(p->last_stream) != hipSuccess) return CS3D_E_DEVICE;
   if (!p->last_stream && hipDeviceSynchronize() != hipSuccess) return CS3D_E_DEVICE;
-  unsigned long long h[2] = {0, 0};
+  unsigned long long h[kStatsWords];
   if (hipMemcpy(h, p->dstats, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CS3D_E_DEVICE;
-  double mp;
-  std::memcpy(&mp, &h[0], 8);
-  out->min_abs_pivot = mp;
+  double d[kStatsWords];
+  std::memcpy(d, h, sizeof(d));
+  out->min_abs_pivot = d[0];
   out->bad_pivots = (int64_t)h[1];
+  out->refine_done = p->refine_done;
+  cs3d_status st = h[1] ? CS3D_E_SINGULAR : CS3D_OK;
+  if (p->d.precision != CS3D_FP64 && p->timed) {
+    const double fn = std::sqrt(d[2]);
+    for (int k = 0; k <= p->refine_done && k < 8; ++k) out->residual_history[k] = std::sqrt(d[3 + k]) / fn;
+    const double last = out->residual_history[p->refine_done < 8 ? p->refine_done : 7];
+    if (st == CS3D_OK && !(last <= kResidualTarget)) st = CS3D_E_NOTCONVERGED;
+  }
   float ms = 0.f;
   if (p->timed && hipEventElapsedTime(&ms, p->ev0, p->ev1) == hipSuccess) out->last_solve_ms = ms;
   const long long n = p->solves < kRing ? p->solves : kRing;
-  out->stage_count = p->nstages;
+  out->stage_count = kStages;
   out->timed_solves = (int)n;
   for (long long q = 0; q < n; ++q)
-    for (int k = 0; k < p->nstages; ++k) {
-      const size_t base = (size_t)q * (kMaxStages + 1);
+    for (int k = 0; k < p->ring_n[q]; ++k) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, p->ring[base + k], p->ring[base + k + 1]) != hipSuccess) return CS3D_E_DEVICE;
-      out->stage_ms[k] += (double)t / (double)n;
+      if (hipEventElapsedTime(&t, p->ring[q * (kMaxMarks + 1) + k], p->ring[q * (kMaxMarks + 1) + k + 1]) !=
+          hipSuccess)
+        return CS3D_E_DEVICE;
+      out->stage_ms[p->ring_sid[q * kMaxMarks + k]] += (double)t / (double)n;
     }
-  return h[1] ? CS3D_E_SINGULAR : CS3D_OK;
+  return st;
 }
 
 extern "C" cs3d_status cs3d_reset_timers(cs3d_plan p) {

@@ -59,6 +59,7 @@ struct ProbDev {
   long long G_stride;
   double* C;           // [nz][nx][ldy]   c' of the tridiagonal LU
   unsigned long long* stats;  // [0] = bits of min |pivot|, [1] = count of bad pivots
+  int accumulate;      // K4: u += result (refinement corrections) instead of u = result
 };
 
 // ---------------------------------------------------------------------------
@@ -584,7 +585,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int i = line_mode<MX, 1>(lane, s, p.nx);
-        if (i > 0) u[i - 1] = p.scale * (double)out[s];
+        if (i > 0) u[i - 1] = p.accumulate ? u[i - 1] + p.scale * (double)out[s] : p.scale * (double)out[s];
       }
     }
   }
@@ -625,11 +626,28 @@ __global__ void __launch_bounds__(256) k_residual(ProbDev p, const double* __res
   R[idx] = F - acc;
 }
 
+// statistics block: [0] bits of min |pivot|, [1] bad pivots, then doubles:
+// [2] ||F||^2, [3 + s] ||r_s||^2 after refinement step s (s = 0 is the initial solve)
+constexpr int kStatsWords = 16;
+
 __global__ void k_stats_reset(unsigned long long* s) {
   if (threadIdx.x == 0) {
     s[0] = 0x7FEFFFFFFFFFFFFFull;  // bits of DBL_MAX
     s[1] = 0ull;
   }
+  if (threadIdx.x >= 2 && threadIdx.x < kStatsWords) s[threadIdx.x] = 0ull;  // +0.0
+}
+
+// acc += sum of squares of x[0..n) (one FP64 atomic per workgroup)
+__global__ void __launch_bounds__(256) k_sumsq(const double* __restrict__ x, long long n, double* acc) {
+  __shared__ double part[4];
+  double s = 0.0;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
+    s += x[e] * x[e];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(acc, part[0] + part[1] + part[2] + part[3]);
 }
 
 }  // namespace cs3d

@@ -144,3 +144,60 @@ def test_paper_table5_on_gpu(cs3d):
     u, _ = _gpu_solve(cs3d, p)
     ue = p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1]
     assert abs(np.abs(u[0] - ue).max() - 3.4493268e-05) < 0.75e-12
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: FP32 line transforms, FP64 tridiagonal LU, FP64 residual refinement
+# ---------------------------------------------------------------------------
+TOL_MIXED = 1e-10
+
+MIXED_CASES = [
+    ("helm6", 63, 127, 33),   # fft64 / fft128
+    ("helm4", 255, 63, 17),   # fft256 / fft64
+    ("cd4", 511, 63, 9),      # fft512 / fft64
+    ("helm6", 63, 1023, 5),   # fft64 / fft1024 (two-wave lines)
+    ("helm6", 30, 17, 9),     # dense / dense
+]
+
+
+@pytest.mark.parametrize("scheme,nx,ny,nz", MIXED_CASES)
+def test_mixed_refined_matches_oracle(cs3d, scheme, nx, ny, nz):
+    p = WL.noise_problem(nx, ny, nz, scheme, seed=2000 + nx + 7 * ny + 13 * nz)
+    print(f"case mixed {scheme} {nx}x{ny}x{nz}", flush=True)
+    dev = torch.device("cuda:0")
+    plan = cs3d.plan_for_problem(p, precision="mixed", refine_steps=2, device=dev)
+    u = plan.solve(p.f.to(dev), p.g_lo.to(dev), p.g_hi.to(dev)).cpu().numpy()
+    st = plan.stats()
+    plan.close()
+    ref = _oracle(p)
+    err = _rel(u[0], ref.U)
+    hist = st["residual_history"][:3]
+    print(f"  rel err {err:.3e}  residual history {hist}", flush=True)
+    assert err < max(TOL_MIXED, _bar(p, ref)), err
+    assert st["refine_done"] == 2
+    assert hist[1] < hist[0] and hist[2] <= hist[1] * 1.01
+    assert hist[2] < 1e-12
+    assert st["status"] == 0
+
+
+def test_mixed_without_refinement_is_fp32_accurate(cs3d):
+    p = WL.noise_problem(127, 63, 20, "helm4", seed=31)
+    dev = torch.device("cuda:0")
+    plan = cs3d.plan_for_problem(p, precision="mixed", refine_steps=0, device=dev)
+    u = plan.solve(p.f.to(dev), p.g_lo.to(dev), p.g_hi.to(dev)).cpu().numpy()
+    st = plan.stats()
+    ref = _oracle(p)
+    err = _rel(u[0], ref.U)
+    # single-precision transforms: error well above FP64, well below 1e-3
+    assert 1e-9 < err < 1e-4, err
+    assert st["refine_done"] == 0 and st["residual_history"][0] > 1e-9
+
+
+def test_mixed_multi_rhs(cs3d):
+    p = WL.noise_problem(63, 63, 24, "helm6", seed=41, nrhs=2)
+    dev = torch.device("cuda:0")
+    plan = cs3d.plan_for_problem(p, precision="mixed", refine_steps=2, device=dev)
+    u = plan.solve(p.f.to(dev), p.g_lo.to(dev), p.g_hi.to(dev)).cpu().numpy()
+    for r in range(2):
+        ref = _oracle(p, r)
+        assert _rel(u[r], ref.U) < max(TOL_MIXED, _bar(p, ref, r))
