@@ -537,15 +537,15 @@ static hipError_t transform_solve(cs3d_plan p, const ProbDev& pd, int nrhs, hipS
 
 static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s);
 
-// r = F - A U and its squared norm into stats word `slot`
+// r = F - A U and its squared norm into stats word `slot` (slot < 0: no norm)
 static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, double* R,
                                 int nrhs, int slot, hipStream_t s) {
-  dim3 grid((p->d.nx + 63) / 64, (p->d.ny + 3) / 4, p->d.nz * nrhs);
+  const int nzc = (p->d.nz + kZChunk - 1) / kZChunk;
+  dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, pd, F, U, R);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return norm_pass(R, (long long)n3(p) * nrhs, reinterpret_cast<double*>(p->dstats) + slot, s);
+  double* acc = slot >= 0 ? reinterpret_cast<double*>(p->dstats) + slot : nullptr;
+  hipLaunchKernelGGL(k_residual, grid, dim3(kRThreads), 0, s, pd, F, U, R, acc);
+  return hipGetLastError();
 }
 
 static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int assembled, const double* glo,
@@ -631,11 +631,9 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   // F (with the lift) goes into r, then r = F - A U in place
   const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
   if (!assembled && run_rhs(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
-  dim3 grid((p->d.nx + 63) / 64, (p->d.ny + 3) / 4, p->d.nz * nrhs);
-  if (grid.z > 65535u || grid.y > 65535u) return CS3D_E_UNSUPPORTED;
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, pd, assembled ? dev_f : (const double*)dev_r, dev_u,
-                     dev_r);
-  return hipGetLastError() == hipSuccess ? CS3D_OK : CS3D_E_DEVICE;
+  return residual_pass(p, pd, assembled ? dev_f : (const double*)dev_r, dev_u, dev_r, nrhs, -1, s) == hipSuccess
+             ? CS3D_OK
+             : CS3D_E_DEVICE;
 }
 
 extern "C" cs3d_status cs3d_get_stats(cs3d_plan p, cs3d_stats* out) {

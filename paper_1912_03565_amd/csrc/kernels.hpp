@@ -592,38 +592,106 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 residual r = F - A U of eq. stencil27 (z-face data as boundary planes).
-// F is the interior right-hand side (lift included).
+// FP64 residual r = F - A U of eq. stencil27 (the z-face data are in F through the
+// lift; U vanishes on every face), with ||r||^2 accumulated into acc.  Tile 64 x 16
+// interior points, 512 threads (two y-rows each), marching over kZChunk planes with a
+// three-plane window of U (halo 1) in LDS and two planes in flight in registers.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_residual(ProbDev p, const double* __restrict__ Fi,
-                                                  const double* __restrict__ U, double* __restrict__ R) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6) + 1;
-  const int l = blockIdx.z % p.nz + 1, r = blockIdx.z / p.nz;
-  if (i > p.nx || j > p.ny) return;
-  const long long idx = r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
-  const double F = Fi[idx];
-  const double* Ur = U + r * p.u_stride;
-  double acc = 0.0;
-  for (int o = -1; o <= 1; ++o) {
-    const int ll = l + o;
-    if (ll < 1 || ll > p.nz) continue;  // boundary planes are in the lift
-    const double* w = p.W + (l - 1) * 12 + (o + 1) * 4;
-    const double* P = Ur + (long long)p.nx * p.ny * (ll - 1);
-    double s = 0.0;
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int jj = j + dj;
-      if (jj < 1 || jj > p.ny) continue;
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = i + di;
-        if (ii < 1 || ii > p.nx) continue;
-        const double wt = (di && dj) ? w[0] : (di ? w[1] : (dj ? w[2] : w[3]));
-        s += wt * P[(ii - 1) + (long long)p.nx * (jj - 1)];
-      }
-    }
-    acc += s;
+constexpr int kQX = 64 + 2, kQY = 16 + 2;
+constexpr int kQLoads = (kQX * kQY + kRThreads - 1) / kRThreads;
+
+__global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double* __restrict__ Fi,
+                                                        const double* __restrict__ U, double* __restrict__ R,
+                                                        double* acc) {
+  __shared__ double win[3][kQX * kQY];
+  __shared__ double part[kRThreads / 64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
+  const int nzc = (p.nz + kZChunk - 1) / kZChunk;
+  const int zc = blockIdx.z % nzc, r = blockIdx.z / nzc;
+  const int lb = 1 + zc * kZChunk;
+  const int le = min(p.nz, lb + kZChunk - 1);
+  const long long plane = (long long)p.nx * p.ny;
+  const double* __restrict__ Ur = U + r * p.u_stride;
+  long long off[kQLoads];
+  bool ok[kQLoads];
+#pragma unroll
+  for (int k = 0; k < kQLoads; ++k) {
+    const int e = threadIdx.x + kRThreads * k;
+    const int yy = e / kQX, xx = e - yy * kQX;
+    const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;  // interior indices, 1-based
+    ok[k] = e < kQX * kQY && gx >= 1 && gx <= p.nx && gy >= 1 && gy <= p.ny;
+    off[k] = ok[k] ? (gx - 1) + (long long)p.nx * (gy - 1) : 0;
   }
-  R[idx] = F - acc;
+  double pa[kQLoads], pb[kQLoads];
+  auto fetch = [&](double(&pre)[kQLoads], int q) {
+    const bool qok = q >= 1 && q <= p.nz;
+#pragma unroll
+    for (int k = 0; k < kQLoads; ++k) pre[k] = (qok && ok[k]) ? Ur[off[k] + plane * (q - 1)] : 0.0;
+  };
+  auto stash = [&](const double(&pre)[kQLoads], int q) {
+    double* w = win[(q + 3) % 3];
+#pragma unroll
+    for (int k = 0; k < kQLoads; ++k) {
+      const int e = threadIdx.x + kRThreads * k;
+      if (e < kQX * kQY) w[e] = pre[k];
+    }
+  };
+  fetch(pa, lb - 1);
+  stash(pa, lb - 1);
+  fetch(pa, lb);
+  stash(pa, lb);
+  fetch(pa, lb + 1);
+  fetch(pb, lb + 2);
+  const int i = x0 + tx;
+  double ss = 0.0;
+  auto compute = [&](int l) {
+    const double* Pm = win[(l + 2) % 3];
+    const double* P0 = win[l % 3];
+    const double* Pp = win[(l + 1) % 3];
+    const double* Wl = p.W + (l - 1) * 12;
+#pragma unroll 1
+    for (int k = 0; k < kRRows; ++k) {
+      const int yl = ty * kRRows + k, j = y0 + yl;
+      if (i > p.nx || j > p.ny) continue;
+      const int c = (yl + 1) * kQX + tx + 1;
+      double au = 0.0;
+      const double* planes[3] = {Pm, P0, Pp};
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        const double* P = planes[o];
+        const double* w = Wl + 4 * o;
+        au += w[0] * (P[c - kQX - 1] + P[c - kQX + 1] + P[c + kQX - 1] + P[c + kQX + 1]) +
+              w[1] * (P[c - 1] + P[c + 1]) + w[2] * (P[c - kQX] + P[c + kQX]) + w[3] * P[c];
+      }
+      const long long idx = r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+      const double rr = Fi[idx] - au;
+      R[idx] = rr;
+      ss += rr * rr;
+    }
+  };
+  for (int l = lb; l <= le; l += 2) {
+    stash(pa, l + 1);
+    __syncthreads();
+    if (l + 2 <= le) fetch(pa, l + 3);
+    compute(l);
+    __syncthreads();
+    if (l + 1 <= le) {
+      stash(pb, l + 2);
+      __syncthreads();
+      if (l + 3 <= le) fetch(pb, l + 4);
+      compute(l + 1);
+      __syncthreads();
+    }
+  }
+  for (int off2 = 32; off2 > 0; off2 >>= 1) ss += __shfl_xor(ss, off2, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0 && acc) {
+    double t = 0.0;
+    for (int q = 0; q < kRThreads / 64; ++q) t += part[q];
+    atomicAdd(acc, t);
+  }
 }
 
 // statistics block: [0] bits of min |pivot|, [1] bad pivots, then doubles:
