@@ -124,6 +124,55 @@ def time_path(cs3d, p, nrhs, precision, steps, warmup, dev):
     return u, ms, st
 
 
+def batch_bench(cs3d, dev, steps, warmup):
+    """64 uneven problems (per-axis sizes from {63, 127, 255}, HELM4/HELM6/CD4 in turn):
+    autotuned, then graph replays timed with HIP events on the solving stream."""
+    import torch
+
+    import workloads as WL
+
+    probs = WL.batch_members(seed=104, count=64, sizes=(63, 127, 255), device=dev)
+    fs = [p.f[0] for p in probs]
+    b = cs3d.Batch([cs3d.batch_member(p) for p in probs], device=dev)
+    us = b.outputs()
+    unknowns = sum(p.nx * p.ny * p.nz for p in probs)
+    b.set_tuning({"graph": 0})
+    b.solve(fs, us)
+    eager = b.stats()
+    tuning, tuned_ms = b.autotune(fs, us, reps=2)
+    b.set_tuning({"graph": 0})
+    b.solve(fs, us)
+    stages = b.stats()["stage_ms"]
+    b.set_tuning({"graph": 1})
+    for _ in range(warmup):
+        b.solve(fs, us)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        b.solve(fs, us)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = b.stats()
+    # algorithmic bytes as for one right-hand side of each member
+    sb = [sum(stage_bytes(p.nx, p.ny, p.nz, 1)[k] for p in probs) for k in range(5)]
+    out = {"workload": "64 problems, per-axis N from {63,127,255}, HELM4/HELM6/CD4, k0~U[5,60], "
+                       "gamma~U[-100,-5], f~U[-1,1], seed 104",
+           "unknowns": unknowns, "ms_per_solve": round(ms, 4), "value": round(unknowns / (ms / 1e3), 1),
+           "unit": "unknowns/s", "graph": True, "tuning": tuning,
+           "untuned_eager_ms": round(sum(eager["stage_ms"]), 4),
+           "stage_ms_eager": [round(x, 4) for x in stages],
+           "algorithmic_GBs": round(sum(sb) / (ms / 1e3) / 1e9, 1),
+           "min_abs_pivot": st["min_abs_pivot"], "bad_pivots": st["bad_pivots"]}
+    log(f"[bench] batch: {ms:.3f} ms per solve of {unknowns} unknowns, tuning {tuning}, stages {stages}")
+    b.close()
+    del us, fs, probs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +183,7 @@ def main():
     ap.add_argument("--cpu-planes", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="after the timed steps, copy 2 GiB once with a plain device copy "
                          "(the reference for scaling HBM byte counters)")
@@ -204,6 +254,10 @@ def main():
         log("[bench] traffic probe: copied 2 GiB")
         del src, dst
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_bench(cs3d, dev, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_planes} planes")
@@ -225,6 +279,7 @@ def main():
         "stages": stages,
         "paths": paths,
         "fp64_path_algorithmic_GBs": round(whole_gbs, 1),
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -155,20 +155,94 @@ cs3d_status cs3d_get_stats(cs3d_plan plan, cs3d_stats* out_stats);
 /* Restart the per-pass timing average reported by cs3d_get_stats.  Errors: E_INVAL. */
 cs3d_status cs3d_reset_timers(cs3d_plan plan);
 
-/* Batches: n independent problems of different sizes, schemes and coefficients solved by
- * one persistent launch per stage over a device work list, captured once into a HIP graph.
- * cs3d_batch_create builds one plan per member (desc[i]); the batch owns them.
- * Each member takes one right-hand side.  The workspace is caller-owned as for plans. */
+/* Launch-shape choices.  Each has a default that needs no tuning; cs3d_autotune and
+ * cs3d_batch_autotune time the candidates on the caller's data and keep the fastest.
+ * zchunk, xpersist, order and graph do not change the arithmetic (results are bitwise the
+ * same for every value); ywpl selects another radix split of the y-line FFT, which changes
+ * the rounding of the transform only. */
+typedef struct {
+  int zchunk;    /* z-planes per workgroup of the z-marching passes (RHS operator and, on the
+                    mixed path, the FP64 residual): 8..512, default 32 */
+  int xpersist;  /* x passes of a plan: 1 = a resident set of workgroups walks all tiles
+                    (default), 0 = one workgroup per tile */
+  int ywpl;      /* y passes of a plan where N_y+1 is 512 or 1024: waves per line, 1 or 2
+                    (default 2 for 1024, 1 otherwise; other sizes always use 1) */
+  int order;     /* batches: 1 = members ordered by decreasing cost per work item in every
+                    pass, so the longest items start first (default); 0 = order given */
+  int graph;     /* batches: 1 = the passes of a solve are captured once into a HIP graph and
+                    replayed (default); 0 = launched one by one, with per-pass timing */
+} cs3d_tuning;
+
+/* Current launch-shape choices of a plan.  Errors: E_INVAL (NULL argument). */
+cs3d_status cs3d_get_tuning(cs3d_plan plan, cs3d_tuning* out);
+
+/* Set the launch-shape choices of a plan (order and graph are ignored).
+ * Errors: E_INVAL (NULL argument or a field out of range). */
+cs3d_status cs3d_set_tuning(cs3d_plan plan, const cs3d_tuning* tuning);
+
+/* Time every candidate of each launch-shape choice on real solves of the caller's data
+ * (reps timed solves per candidate after one warm-up solve; each choice is judged by the
+ * device time of the passes it affects) and keep the fastest.  The arguments are those of
+ * cs3d_solve; dev_u receives a solution.  Synchronises the stream.  *out_best (may be NULL)
+ * receives the choice, *out_ms (may be NULL) the mean time of one solve with it.
+ * Errors: as cs3d_solve; E_INVAL for reps < 1. */
+cs3d_status cs3d_autotune(cs3d_plan plan, int nrhs, const double* dev_f, const double* dev_g_lo,
+                          const double* dev_g_hi, double* dev_u, void* hip_stream, int reps,
+                          cs3d_tuning* out_best, double* out_ms);
+
+/* Batches: n independent problems, each with its own sizes, steps, scheme and
+ * coefficients (desc[i]; max_rhs is ignored, every member takes one right-hand side,
+ * precision must be CS3D_FP64, scheme must not be CS3D_WEIGHTS), solved together.  Every
+ * pass of Section 3.6 (RHS operator and lift, x-DST, y-DST with forward elimination, back
+ * substitution with inverse y-DST, inverse x-DST) is ONE launch over the work items of all
+ * members (tiles, line groups), taken by a resident set of workgroups from a device work
+ * list; the five launches are captured once into a HIP graph and replayed.  Each member
+ * goes through the per-item code of a plan built from its desc (default y-line split).
+ * The z-face data are zero.
+ * Errors: E_INVAL (n < 1, NULL pointers, a desc rejected by cs3d_plan_create or
+ * CS3D_WEIGHTS), E_UNSUPPORTED (mixed precision), E_NOMEM, E_DEVICE. */
 cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hip_stream, cs3d_batch* out);
+
+/* Bytes of device workspace of the batch (the members' workspaces back to back). */
 size_t cs3d_batch_workspace_bytes(cs3d_batch batch);
+
+/* Caller-owned device workspace, 256-byte aligned, at least cs3d_batch_workspace_bytes.
+ * Errors: E_INVAL (NULL, misaligned), E_WORKSPACE (too small). */
 cs3d_status cs3d_batch_set_workspace(cs3d_batch batch, void* dev_workspace, size_t bytes);
-/* dev_f[i] / dev_u[i]: device pointers of member i (closed-grid f, interior u).  The
- * pointer arrays themselves are host arrays.  The first call with a given set of
- * pointers captures the launches into a HIP graph; later calls with the same pointers
- * replay it. */
+
+/* Solve every member: dev_f[i] is member i's closed-grid f, dev_u[i] its interior solution
+ * (device pointers; the two pointer arrays are host arrays of n entries, read during the
+ * call).  Asynchronous on hip_stream.  When a pointer differs from the previous call the
+ * member table is uploaded again on that stream before the launches; the captured graph is
+ * kept.  Calls on one batch must be ordered (one stream, or synchronised by the caller).
+ * Errors: E_INVAL (NULL argument or member pointer), E_WORKSPACE, E_DEVICE. */
 cs3d_status cs3d_batch_solve(cs3d_batch batch, const double* const* dev_f, double* const* dev_u,
                              void* hip_stream);
+
+/* Statistics of the last batch solve (synchronises): min |pivot| over all members and the
+ * total count of bad pivots; last_solve_ms; stage_ms of the five passes when the last solve
+ * was launched pass by pass (graph = 0), else stage_count = 0.  Returns E_SINGULAR when a
+ * member met a zero or non-finite pivot. */
 cs3d_status cs3d_batch_get_stats(cs3d_batch batch, cs3d_stats* out_stats);
+
+/* Pivot statistics of member i of the last batch solve (min_abs_pivot, bad_pivots; the
+ * timing fields are those of the batch).  Errors: E_INVAL (index out of range). */
+cs3d_status cs3d_batch_member_stats(cs3d_batch batch, int i, cs3d_stats* out_stats);
+
+/* Launch-shape choices of a batch (zchunk, order, graph; xpersist and ywpl are ignored:
+ * batch passes are always resident and use the default waves per line).  Setting them
+ * rebuilds the work lists and drops the captured graph.
+ * Errors: E_INVAL (NULL argument or a field out of range), E_DEVICE. */
+cs3d_status cs3d_batch_get_tuning(cs3d_batch batch, cs3d_tuning* out);
+cs3d_status cs3d_batch_set_tuning(cs3d_batch batch, const cs3d_tuning* tuning);
+
+/* As cs3d_autotune for a batch: times zchunk and order candidates with per-pass timing,
+ * then enables graph replay.  The arguments are those of cs3d_batch_solve.
+ * Errors: as cs3d_batch_solve; E_INVAL for reps < 1. */
+cs3d_status cs3d_batch_autotune(cs3d_batch batch, const double* const* dev_f, double* const* dev_u,
+                                void* hip_stream, int reps, cs3d_tuning* out_best, double* out_ms);
+
+/* Free the batch's member tables, work lists and graph.  NULL is accepted. */
 cs3d_status cs3d_batch_destroy(cs3d_batch batch);
 
 /* Static text for a status code. */

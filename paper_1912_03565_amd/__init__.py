@@ -6,4 +6,5 @@ x and y, N_x N_y tridiagonal LU solves along z, inverse DST - as hand-written HI
 kernels for gfx950 behind the C ABI of include/cs3d.h.
 """
 from .native import CS3DError, lib  # noqa: F401  (raises ImportError if not built)
-from .solver import Plan, plan_for_problem  # noqa: F401
+from .solver import Batch, Plan, batch_member, plan_for_problem  # noqa: F401
+from .tuning import tuned_batch, tuned_plan  # noqa: F401

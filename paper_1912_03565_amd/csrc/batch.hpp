@@ -1,0 +1,213 @@
+// batch.hpp - grouped passes over many independent problems (batches).
+//
+// A batch of members (problems of any size, scheme and coefficients, one right-hand
+// side each) is solved by one launch per pass.  Every pass has a work list: the k-th
+// member of the pass's order, perm[k], owns items start[k] .. start[k+1]-1 (tiles of
+// the x passes and of the z-marching RHS pass, line groups of the y passes).
+// Workgroups are resident and walk the items blockIdx.x, blockIdx.x + gridDim.x, ...;
+// each item finds its member by binary search in start[] and runs the same per-item
+// code as a single solve, dispatched on the member's line-transform size.  With the
+// members ordered by decreasing cost per item, the long items are taken first.
+#pragma once
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace cs3d {
+
+struct BatchArgs {
+  const ProbDev* P;  // [n] member descriptors (device)
+  const int* start;  // [n + 1] item prefix sums of this pass, in the pass's member order (device)
+  const int* perm;   // [n] member of each position of that order (device)
+  int n;
+  int total;
+};
+
+// position k of the work list holding `item` (start[k] <= item < start[k+1])
+__device__ __forceinline__ int find_slot(const BatchArgs& b, int item) {
+  int lo = 0, hi = b.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.start[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// statistics blocks of all members
+__global__ void kb_stats_reset(unsigned long long* s, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * kStatsWords) return;
+  const int w = e % kStatsWords;
+  s[e] = w == 0 ? 0x7FEFFFFFFFFFFFFFull : 0ull;  // bits of DBL_MAX, then zeros
+}
+
+// x-pass items: tiles of 8 y-lines of one plane
+__host__ __device__ inline int x_items(int ldy, int nz) { return (ldy / kTileJ) * nz; }
+// y-pass items: groups of LPB lines (x-modes)
+__host__ __device__ inline int y_items(int nx, int lpb) { return (nx + lpb - 1) / lpb; }
+// RHS items: 64 x 16 tiles times z-chunks
+__host__ __device__ inline int rhs_items(int nx, int ny, int nz, int zchunk) {
+  return ((nx + kRX - 1) / kRX) * ((ny + kRY - 1) / kRY) * ((nz + zchunk - 1) / zchunk);
+}
+
+// Call fn(std::integral_constant<int, M>) for the member's transform size: FFT lengths up
+// to MAXM, 0 for the dense sine sums when DENSE (a variant without them keeps the
+// register budget of the FFT code; the host picks it only when no member needs them).
+template <int MAXM, bool DENSE, typename Fn>
+__device__ __forceinline__ void dispatch_m(int M, Fn&& fn) {
+  switch (M) {
+    case 64: fn(std::integral_constant<int, 64>{}); break;
+    case 128: fn(std::integral_constant<int, 128>{}); break;
+    case 256: fn(std::integral_constant<int, 256>{}); break;
+    case 512:
+      if constexpr (MAXM >= 512) fn(std::integral_constant<int, 512>{});
+      break;
+    case 1024:
+      if constexpr (MAXM >= 1024) fn(std::integral_constant<int, 1024>{});
+      break;
+    default:
+      if constexpr (DENSE) fn(std::integral_constant<int, 0>{});
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// RHS pass
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
+  __shared__ double win[5][kSY * kSX];
+  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+    const int k = find_slot(b, item);
+    const ProbDev& p = b.P[b.perm[k]];
+    const int t = item - b.start[k];
+    const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRY - 1) / kRY;
+    rhs_block(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x passes: the twiddle tables sit at the start of the LDS, the line buffers after them
+// ---------------------------------------------------------------------------
+template <typename T, int MX>
+__device__ __forceinline__ void xfwd_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
+  constexpr int NS = Tx<MX, 1>::NS;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int ts = tile_stride(p.nx);
+  T* buf = lines + w * bufn;
+  const XTile x = decode_xtile(p, t, w);
+  if (x.active) {
+    const double* Fr = p.F + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
+    if (lane == 0) buf[lp(0)] = (T)0;
+    for (int i = 1 + lane; i <= p.nx; i += 64) buf[lp(i)] = (T)Fr[i - 1];
+  }
+  __syncthreads();
+  T out[NS];
+  if (x.active) line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
+  __syncthreads();
+  if (x.active) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int n = line_mode<MX, 1>(lane, s, p.nx);
+      if (n > 0) lines[w * ts + n] = out[s];
+    }
+  } else {
+    for (int n = 1 + lane; n <= p.nx; n += 64) lines[w * ts + n] = (T)0;
+  }
+  __syncthreads();
+  T* G = reinterpret_cast<T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
+  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
+    const int n0 = idx / kTileJ, jj = idx % kTileJ;
+    G[(long long)n0 * p.ldy + jj] = lines[jj * ts + n0 + 1];
+  }
+  __syncthreads();
+}
+
+template <typename T, int MX>
+__device__ __forceinline__ void xinv_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
+  constexpr int NS = Tx<MX, 1>::NS;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int ts = tile_stride(p.nx);
+  T* buf = lines + w * bufn;
+  const XTile x = decode_xtile(p, t, w);
+  const T* G = reinterpret_cast<const T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
+  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
+    const int n0 = idx / kTileJ, jj = idx % kTileJ;
+    lines[jj * ts + n0 + 1] = G[(long long)n0 * p.ldy + jj];
+  }
+  __syncthreads();
+  T out[NS];
+  line_dst<T, MX, 1, true>(buf, p.nx, out, lane, tab, p.sinx, lines + w * ts);
+  if (x.active) {
+    double* u = p.u + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = line_mode<MX, 1>(lane, s, p.nx);
+      if (i > 0) u[i - 1] = p.scale * (double)out[s];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int MAXM, bool DENSE, bool FWD>
+__global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
+  T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
+  int curM = -1;
+  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+    const int k = find_slot(b, item);
+    const ProbDev& p = b.P[b.perm[k]];
+    const int t = item - b.start[k];
+    if (p.fx != curM) {  // uniform: reload the tables of this transform size
+      __syncthreads();
+      dispatch_m<MAXM, DENSE>(p.fx, [&](auto mc) {
+        constexpr int MM = decltype(mc)::value;
+        if constexpr (MM != 0) load_twiddles<T, MM, 1>(tab, p.twx);
+      });
+      __syncthreads();
+      curM = p.fx;
+    }
+    dispatch_m<MAXM, DENSE>(p.fx, [&](auto mc) {
+      constexpr int MM = decltype(mc)::value;
+      if constexpr (FWD) xfwd_item<T, MM>(p, t, lines, tab);
+      else xinv_item<T, MM>(p, t, lines, tab);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y passes (default waves per line of each size)
+// ---------------------------------------------------------------------------
+template <typename T, int MAXM, bool DENSE, bool FWD>
+__global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
+  T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
+  int curM = -1;
+  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+    const int k = find_slot(b, item);
+    const ProbDev& p = b.P[b.perm[k]];
+    const int g = item - b.start[k];
+    __syncthreads();  // every line of the previous item is done with the LDS
+    if (p.fy != curM) {
+      dispatch_m<MAXM, DENSE>(p.fy, [&](auto mc) {
+        constexpr int MM = decltype(mc)::value;
+        if constexpr (MM != 0) load_twiddles<T, MM, default_wpl<MM>()>(tab, p.twy);
+      });
+      __syncthreads();
+      curM = p.fy;
+    }
+    dispatch_m<MAXM, DENSE>(p.fy, [&](auto mc) {
+      constexpr int MM = decltype(mc)::value;
+      if constexpr (FWD) yfwd_block<T, MM, default_wpl<MM>()>(p, g, 0, lines, tab);
+      else yback_block<T, MM, default_wpl<MM>()>(p, g, 0, lines, tab);
+    });
+  }
+}
+
+}  // namespace cs3d

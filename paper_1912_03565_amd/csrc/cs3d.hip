@@ -7,6 +7,7 @@
 // stream, plus a tiny statistics reset.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "../../include/cs3d.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 
 using namespace cs3d;
@@ -42,8 +44,19 @@ hipError_t dalloc(P** p, size_t count) {
 
 }  // namespace
 
+// Launch-shape choices of a plan or batch (defaults, cs3d_autotune or cs3d_set_tuning)
+struct Tuning {
+  int zchunk = kZChunk;  // planes per workgroup of the z-marching passes
+  int xpersist = 1;      // x passes: 1 = one resident workgroup set walking all tiles,
+                         // 0 = one workgroup per tile
+  int ywpl = 2;          // waves per y-line where the FFT allows two (M >= 512)
+  int order = 1;         // batches: members by decreasing cost per item
+  int graph = 1;         // batches: captured graph replay
+};
+
 struct cs3d_plan_s {
   cs3d_desc d{};
+  Tuning tune;
   int Mx = 0, My = 0, fx = 0, fy = 0, ldy = 0;
   double* dW = nullptr;
   double* dLC = nullptr;
@@ -258,6 +271,7 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   p->fx = fft_len(desc->nx);
   p->fy = fft_len(desc->ny);
   p->ldy = ((desc->ny + 1 + 15) / 16) * 16;
+  p->tune.ywpl = (p->fy == 1024) ? 2 : 1;
   st = build_weights(*desc, p->hW);
   if (st != CS3D_OK) {
     plan_free(p);
@@ -302,10 +316,6 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   CS3D_TRY(hipMemcpyAsync(p->dsiny, sy.data(), sy.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipEventCreate(&p->ev0));
   CS3D_TRY(hipEventCreate(&p->ev1));
-  p->ring.assign((size_t)kRing * (kMaxMarks + 1), nullptr);
-  p->ring_sid.assign((size_t)kRing * kMaxMarks, 0);
-  p->ring_n.assign(kRing, 0);
-  for (hipEvent_t& e : p->ring) CS3D_TRY(hipEventCreate(&e));
   k_stats_reset<<<1, 64, 0, s>>>(p->dstats);
   CS3D_TRY(hipGetLastError());
   // the host vectors above go out of scope: wait for the copies
@@ -361,9 +371,9 @@ static size_t lds_bytes_x_t(const cs3d_plan p) {
   return (a > b ? a : b) + tw_bytes<T, MX>();
 }
 
-template <typename T, int MY>
+template <typename T, int MY, int WPL = default_wpl<MY>()>
 static size_t lds_bytes_y_t(const cs3d_plan p) {
-  return (size_t)YCfg<MY>::LPB * line_buf_elems<T, MY>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
+  return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
 }
 
 template <typename KernelT, typename... Args>
@@ -401,7 +411,7 @@ static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = resident_blocks(k_fwd_x<T, MX>, 64 * kTileJ, lds, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX>, 64 * kTileJ, lds, ntiles) : ntiles;
   return launch(k_fwd_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
@@ -412,20 +422,37 @@ static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = resident_blocks(k_inv_x<T, MX>, 64 * kTileJ, lds, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_inv_x<T, MX>, 64 * kTileJ, lds, ntiles) : ntiles;
   return launch(k_inv_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
+template <typename T, int MY, int WPL>
+static hipError_t run_y_fwd_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  dim3 grid((p->d.nx + YCfg<MY, WPL>::LPB - 1) / YCfg<MY, WPL>::LPB, nrhs), block(kBlockY);
+  return launch(k_fwd_y<T, MY, WPL>, grid, block, lds_bytes_y_t<T, MY, WPL>(p), s, pd);
+}
+
+template <typename T, int MY, int WPL>
+static hipError_t run_y_back_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  dim3 grid((p->d.nx + YCfg<MY, WPL>::LPB - 1) / YCfg<MY, WPL>::LPB, nrhs), block(kBlockY);
+  return launch(k_back_y<T, MY, WPL>, grid, block, lds_bytes_y_t<T, MY, WPL>(p), s, pd);
+}
+
+// waves per y-line: the tuned choice where two are possible (M >= 512), else one
 template <typename T, int MY>
 static hipError_t run_y_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + YCfg<MY>::LPB - 1) / YCfg<MY>::LPB, nrhs), block(kBlockY);
-  return launch(k_fwd_y<T, MY>, grid, block, lds_bytes_y_t<T, MY>(p), s, pd);
+  if constexpr (MY >= 512) {
+    if (p->tune.ywpl == 2) return run_y_fwd_w<T, MY, 2>(p, pd, nrhs, s);
+  }
+  return run_y_fwd_w<T, MY, 1>(p, pd, nrhs, s);
 }
 
 template <typename T, int MY>
 static hipError_t run_y_back_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + YCfg<MY>::LPB - 1) / YCfg<MY>::LPB, nrhs), block(kBlockY);
-  return launch(k_back_y<T, MY>, grid, block, lds_bytes_y_t<T, MY>(p), s, pd);
+  if constexpr (MY >= 512) {
+    if (p->tune.ywpl == 2) return run_y_back_w<T, MY, 2>(p, pd, nrhs, s);
+  }
+  return run_y_back_w<T, MY, 1>(p, pd, nrhs, s);
 }
 
 #define CS3D_DISPATCH(fn, M, ...)                 \
@@ -457,7 +484,7 @@ static hipError_t run_y_back(const cs3d_plan p, const ProbDev& pd, int nrhs, hip
 #undef CS3D_DISPATCH
 
 static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  const int nzc = (p->d.nz + kZChunk - 1) / kZChunk;
+  const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreads), 0, s, pd);
@@ -472,6 +499,8 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.nz = p->d.nz;
   pd.Mx = p->Mx;
   pd.My = p->My;
+  pd.fx = p->fx;
+  pd.fy = p->fy;
   pd.ldy = p->ldy;
   pd.scheme = p->d.scheme;
   pd.hx = p->d.hx;
@@ -501,7 +530,22 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.G_stride = (long long)g_elems(p);
   pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) + off_C(p, nrhs)) : nullptr;
   pd.stats = p->dstats;
+  pd.zchunk = p->tune.zchunk;
   return pd;
+}
+
+// The timing ring is created by the first solve of a plan (plans made for batch members
+// never solve on their own and hold no ring).
+static hipError_t ensure_ring(cs3d_plan p) {
+  if (!p->ring.empty()) return hipSuccess;
+  p->ring.assign((size_t)kRing * (kMaxMarks + 1), nullptr);
+  p->ring_sid.assign((size_t)kRing * kMaxMarks, 0);
+  p->ring_n.assign(kRing, 0);
+  for (hipEvent_t& e : p->ring) {
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+  }
+  return hipSuccess;
 }
 
 // Interval timing: mark(stage) starts an interval of that stage, end_solve closes the last.
@@ -540,7 +584,7 @@ static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream
 // r = F - A U and its squared norm into stats word `slot` (slot < 0: no norm)
 static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, double* R,
                                 int nrhs, int slot, hipStream_t s) {
-  const int nzc = (p->d.nz + kZChunk - 1) / kZChunk;
+  const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
   double* acc = slot >= 0 ? reinterpret_cast<double*>(p->dstats) + slot : nullptr;
@@ -556,6 +600,7 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   if (!p->ws || p->ws_bytes < cs3d_workspace_bytes(p, nrhs)) return CS3D_E_WORKSPACE;
   if (assembled && f == u) return CS3D_E_INVAL;  // F must stay intact until K1 has read all of it
   hipStream_t s = (hipStream_t)hip_stream;
+  if (ensure_ring(p) != hipSuccess) return CS3D_E_DEVICE;
   p->last_stream = s;
   p->cur_marks = 0;
   const bool mixed = p->d.precision != CS3D_FP64;
@@ -695,35 +740,346 @@ extern "C" const char* cs3d_status_str(cs3d_status st) {
 
 extern "C" const char* cs3d_version(void) { return "cs3d 0.1 (gfx950)"; }
 
+
 // ---------------------------------------------------------------------------
-// Batches (first version: one plan per member, launched back to back).
+// Launch-shape choices and the autotuner
 // ---------------------------------------------------------------------------
+static bool tuning_ok(const cs3d_tuning* t) {
+  return t && t->zchunk >= 8 && t->zchunk <= 512 && (t->xpersist == 0 || t->xpersist == 1) &&
+         (t->ywpl == 1 || t->ywpl == 2) && (t->order == 0 || t->order == 1) && (t->graph == 0 || t->graph == 1);
+}
+
+static void tuning_out(const Tuning& t, cs3d_tuning* o) {
+  o->zchunk = t.zchunk;
+  o->xpersist = t.xpersist;
+  o->ywpl = t.ywpl;
+  o->order = t.order;
+  o->graph = t.graph;
+}
+
+extern "C" cs3d_status cs3d_get_tuning(cs3d_plan p, cs3d_tuning* out) {
+  if (!p || !out) return CS3D_E_INVAL;
+  tuning_out(p->tune, out);
+  return CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_set_tuning(cs3d_plan p, const cs3d_tuning* t) {
+  if (!p || !tuning_ok(t)) return CS3D_E_INVAL;
+  p->tune.zchunk = t->zchunk;
+  p->tune.xpersist = t->xpersist;
+  p->tune.ywpl = t->ywpl;
+  return CS3D_OK;
+}
+
+// Mean per-pass device times of `reps` solves with tuning t (after one untimed solve).
+static cs3d_status timed_solves(cs3d_plan p, const Tuning& t, int nrhs, const double* f, const double* glo,
+                                const double* ghi, double* u, void* s, int reps, double (&stage)[8]) {
+  p->tune = t;
+  cs3d_status st = cs3d_solve(p, nrhs, f, glo, ghi, u, s);
+  if (st != CS3D_OK) return st;
+  if ((st = cs3d_reset_timers(p)) != CS3D_OK) return st;
+  for (int k = 0; k < reps; ++k)
+    if ((st = cs3d_solve(p, nrhs, f, glo, ghi, u, s)) != CS3D_OK) return st;
+  cs3d_stats S;
+  st = cs3d_get_stats(p, &S);
+  if (st == CS3D_E_DEVICE || st == CS3D_E_INVAL) return st;
+  for (int k = 0; k < 8; ++k) stage[k] = S.stage_ms[k];
+  return CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_autotune(cs3d_plan p, int nrhs, const double* f, const double* glo, const double* ghi,
+                                     double* u, void* s, int reps, cs3d_tuning* out_best, double* out_ms) {
+  if (!p || reps < 1) return CS3D_E_INVAL;
+  Tuning best = p->tune;
+  double stage[8];
+  cs3d_status st;
+  // each choice is judged by the passes it shapes; the others keep their current choice
+  struct Axis {
+    int Tuning::*field;
+    std::vector<int> values;
+    std::vector<int> stages;
+  };
+  std::vector<Axis> axes;
+  axes.push_back({&Tuning::zchunk, {16, 32, 64, 128}, {0, 5}});
+  axes.push_back({&Tuning::xpersist, {0, 1}, {1, 4}});
+  if (p->fy >= 512) axes.push_back({&Tuning::ywpl, {1, 2}, {2, 3}});
+  for (const Axis& a : axes) {
+    double best_t = INFINITY;
+    int best_v = best.*(a.field);
+    for (int v : a.values) {
+      Tuning t = best;
+      t.*(a.field) = v;
+      if ((st = timed_solves(p, t, nrhs, f, glo, ghi, u, s, reps, stage)) != CS3D_OK) {
+        p->tune = best;
+        return st;
+      }
+      double tt = 0.0;
+      for (int k : a.stages) tt += stage[k];
+      if (tt < best_t) {
+        best_t = tt;
+        best_v = v;
+      }
+    }
+    best.*(a.field) = best_v;
+  }
+  if ((st = timed_solves(p, best, nrhs, f, glo, ghi, u, s, reps, stage)) != CS3D_OK) return st;
+  p->tune = best;
+  if (out_best) tuning_out(best, out_best);
+  if (out_ms) {
+    double tt = 0.0;
+    for (int k = 0; k < kStages; ++k) tt += stage[k];
+    *out_ms = tt;
+  }
+  return CS3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: each pass is one launch over the work items of all members (batch.hpp),
+// the five launches captured once into a HIP graph.
+// ---------------------------------------------------------------------------
+namespace {
+enum BatchPass { kPassRhs = 0, kPassXf, kPassYf, kPassYb, kPassXi, kPasses };
+}
+
 struct cs3d_batch_s {
-  std::vector<cs3d_plan> plans;
-  std::vector<size_t> offs;
+  int n = 0;
+  std::vector<cs3d_plan> plans;  // member tables (weights, cosines, twiddles)
+  std::vector<size_t> offs;      // workspace offset of each member
   size_t bytes = 0;
   void* ws = nullptr;
+  int general = 0;               // kernel variant: 0 = FFT lengths 64..256 only,
+                                 // 1 = every transform (FFT up to 1024 and dense sums)
+  Tuning tune;
+  std::vector<const double*> cur_f;
+  std::vector<double*> cur_u;
+  bool have_ptrs = false;        // dP holds the descriptors of cur_f / cur_u
+  ProbDev* hP = nullptr;         // pinned staging of the member descriptors
+  ProbDev* dP = nullptr;
+  int* dlist = nullptr;          // per pass: start[n + 1], perm[n]
+  unsigned long long* dstats = nullptr;  // n x kStatsWords
+  int total[kPasses] = {};
+  int grid[kPasses] = {};
+  size_t lds[kPasses] = {};
+  bool ready = false;            // work lists and grids match tune
+  hipEvent_t up_ev = nullptr;    // the last upload of hP has been read
+  bool up_pending = false;
+  hipStream_t cap = nullptr;     // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[kPasses + 1] = {};
+  hipEvent_t tev0 = nullptr, tev1 = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool timed = false, staged = false;
 };
+
+static int list_stride(const cs3d_batch b) { return 2 * b->n + 1; }
+
+// relative cost of one line transform of N points (FFT of length f, or dense sums)
+static double line_cost(int f, int N) { return f ? f * std::log2((double)f) : 0.25 * (double)N * N; }
+
+static int y_wpl(int fy) { return fy == 1024 ? 2 : 1; }
+
+// LDS elements (doubles) of one line buffer, as line_buf_elems for T = double
+static size_t line_elems(int f, int N) { return (size_t)(f ? lp(f) : lp(((N + 1 + 63) / 64) * 64)); }
+
+template <int MAXM, bool DENSE>
+static cs3d_status batch_grids_t(cs3d_batch b) {
+  size_t lx = 0, ly = 0;
+  for (cs3d_plan q : b->plans) {
+    const size_t ts = (size_t)tile_stride(q->d.nx);
+    const size_t bx = line_elems(q->fx, q->d.nx);
+    lx = std::max(lx, (size_t)kTileJ * std::max(bx, ts) * 8);
+    ly = std::max(ly, (size_t)(kBlockY / (64 * y_wpl(q->fy))) * line_elems(q->fy, q->d.ny) * 8);
+  }
+  const size_t tw = (size_t)tw_entries<MAXM>() * sizeof(cx<double>);
+  b->lds[kPassRhs] = 0;
+  b->lds[kPassXf] = b->lds[kPassXi] = tw + lx;
+  b->lds[kPassYf] = b->lds[kPassYb] = tw + ly;
+  const void* kern[kPasses] = {reinterpret_cast<const void*>(kb_rhs),
+                               reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, true>),
+                               reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, true>),
+                               reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, false>),
+                               reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, false>)};
+  const int threads[kPasses] = {kRThreads, 64 * kTileJ, kBlockY, kBlockY, 64 * kTileJ};
+  for (int k = 0; k < kPasses; ++k) {
+    if (b->lds[k] > 160 * 1024) return CS3D_E_UNSUPPORTED;
+    if (b->lds[k] > 64 * 1024 &&
+        hipFuncSetAttribute(kern[k], hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds[k]) != hipSuccess)
+      return CS3D_E_DEVICE;
+    b->grid[k] = b->total[k] > 0 ? resident_blocks(kern[k], threads[k], b->lds[k], b->total[k]) : 0;
+  }
+  return CS3D_OK;
+}
+
+// Work lists of every pass (member order and item prefix sums) and the resident grids.
+static cs3d_status batch_prepare(cs3d_batch b) {
+  const int n = b->n;
+  std::vector<int> host((size_t)kPasses * list_stride(b));
+  for (int pass = 0; pass < kPasses; ++pass) {
+    std::vector<long long> items(n);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) {
+      const cs3d_plan q = b->plans[i];
+      const int nx = q->d.nx, ny = q->d.ny, nz = q->d.nz;
+      switch (pass) {
+        case kPassRhs:
+          items[i] = rhs_items(nx, ny, nz, b->tune.zchunk);
+          cost[i] = std::min(nz, b->tune.zchunk);
+          break;
+        case kPassXf:
+        case kPassXi:
+          items[i] = x_items(q->ldy, nz);
+          cost[i] = line_cost(q->fx, nx);
+          break;
+        default:
+          items[i] = y_items(nx, kBlockY / (64 * y_wpl(q->fy)));
+          cost[i] = nz * line_cost(q->fy, ny) / y_wpl(q->fy);
+          break;
+      }
+    }
+    std::vector<int> perm(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    if (b->tune.order)
+      std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    int* st = host.data() + (size_t)pass * list_stride(b);
+    long long acc = 0;
+    st[0] = 0;
+    for (int k = 0; k < n; ++k) {
+      acc += items[perm[k]];
+      if (acc > 0x7FFFFFFFLL) return CS3D_E_UNSUPPORTED;
+      st[k + 1] = (int)acc;
+      st[n + 1 + k] = perm[k];
+    }
+    b->total[pass] = (int)acc;
+  }
+  if (hipMemcpy(b->dlist, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return CS3D_E_DEVICE;
+  const cs3d_status st = b->general ? batch_grids_t<1024, true>(b) : batch_grids_t<256, false>(b);
+  if (st != CS3D_OK) return st;
+  b->ready = true;
+  return CS3D_OK;
+}
+
+template <int MAXM, bool DENSE>
+static hipError_t batch_pass_t(const cs3d_batch b, int pass, hipStream_t s) {
+  if (b->total[pass] == 0) return hipSuccess;
+  const int* lst = b->dlist + (size_t)pass * list_stride(b);
+  const BatchArgs a{b->dP, lst, lst + b->n + 1, b->n, b->total[pass]};
+  const dim3 g(b->grid[pass]);
+  switch (pass) {
+    case kPassRhs: hipLaunchKernelGGL(kb_rhs, g, dim3(kRThreads), 0, s, a); break;
+    case kPassXf: hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, true>), g, dim3(64 * kTileJ), b->lds[pass], s, a); break;
+    case kPassYf: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, true>), g, dim3(kBlockY), b->lds[pass], s, a); break;
+    case kPassYb: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, false>), g, dim3(kBlockY), b->lds[pass], s, a); break;
+    default: hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, false>), g, dim3(64 * kTileJ), b->lds[pass], s, a); break;
+  }
+  return hipGetLastError();
+}
+
+// statistics reset + the five passes; with events between the passes when `marks`
+static hipError_t batch_launch(const cs3d_batch b, hipStream_t s, bool marks) {
+  hipError_t e;
+  const int words = b->n * kStatsWords;
+  hipLaunchKernelGGL(kb_stats_reset, dim3((words + 255) / 256), dim3(256), 0, s, b->dstats, b->n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 0; k < kPasses; ++k) {
+    if ((e = b->general ? batch_pass_t<1024, true>(b, k, s) : batch_pass_t<256, false>(b, k, s)) != hipSuccess)
+      return e;
+    if (marks && (e = hipEventRecord(b->ev[k + 1], s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static void batch_drop_graph(cs3d_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static cs3d_status batch_capture(cs3d_batch b) {
+  if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return CS3D_E_DEVICE;
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return CS3D_E_DEVICE;
+  const hipError_t e = batch_launch(b, b->cap, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return CS3D_E_DEVICE;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    batch_drop_graph(b);
+    return CS3D_E_DEVICE;
+  }
+  return CS3D_OK;
+}
+
+static void batch_free(cs3d_batch b) {
+  if (!b) return;
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  if (b->up_pending) (void)hipEventSynchronize(b->up_ev);
+  batch_drop_graph(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->tev0) (void)hipEventDestroy(b->tev0);
+  if (b->tev1) (void)hipEventDestroy(b->tev1);
+  if (b->up_ev) (void)hipEventDestroy(b->up_ev);
+  if (b->dP) (void)hipFree(b->dP);
+  if (b->dlist) (void)hipFree(b->dlist);
+  if (b->dstats) (void)hipFree(b->dstats);
+  if (b->hP) (void)hipHostFree(b->hP);
+  for (cs3d_plan q : b->plans) cs3d_plan_destroy(q);
+  delete b;
+}
 
 extern "C" cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hip_stream, cs3d_batch* out) {
   if (!out || n < 1 || !descs) return CS3D_E_INVAL;
   *out = nullptr;
+  for (int i = 0; i < n; ++i) {  // every description is checked before any allocation
+    cs3d_desc d = descs[i];
+    d.max_rhs = 1;
+    const cs3d_status st = validate(&d);
+    if (st != CS3D_OK) return st;
+    if (d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
+    if (d.precision != CS3D_FP64) return CS3D_E_UNSUPPORTED;
+  }
   cs3d_batch b = new (std::nothrow) cs3d_batch_s();
   if (!b) return CS3D_E_NOMEM;
+  b->n = n;
   size_t off = 0;
+  bool small = true;  // every transform an FFT of length 64..256
   for (int i = 0; i < n; ++i) {
+    cs3d_desc d = descs[i];
+    d.max_rhs = 1;
     cs3d_plan p = nullptr;
-    cs3d_status st = cs3d_plan_create(&descs[i], hip_stream, &p);
+    const cs3d_status st = cs3d_plan_create(&d, hip_stream, &p);
     if (st != CS3D_OK) {
-      for (cs3d_plan q : b->plans) cs3d_plan_destroy(q);
-      delete b;
+      batch_free(b);
       return st;
     }
     b->plans.push_back(p);
     b->offs.push_back(off);
     off += round256(cs3d_workspace_bytes(p, 1));
+    small = small && p->fx && p->fy && p->fx <= 256 && p->fy <= 256;
   }
   b->bytes = off;
+  b->general = small ? 0 : 1;
+  b->cur_f.assign(n, nullptr);
+  b->cur_u.assign(n, nullptr);
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&b->hP), n * sizeof(ProbDev)) == hipSuccess &&
+            dalloc(&b->dP, n) == hipSuccess && dalloc(&b->dlist, (size_t)kPasses * list_stride(b)) == hipSuccess &&
+            dalloc(&b->dstats, (size_t)n * kStatsWords) == hipSuccess &&
+            hipEventCreateWithFlags(&b->up_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreate(&b->tev0) == hipSuccess && hipEventCreate(&b->tev1) == hipSuccess;
+  for (hipEvent_t& e : b->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    batch_free(b);
+    return CS3D_E_DEVICE;
+  }
   *out = b;
   return CS3D_OK;
 }
@@ -733,43 +1089,208 @@ extern "C" size_t cs3d_batch_workspace_bytes(cs3d_batch b) { return b ? b->bytes
 extern "C" cs3d_status cs3d_batch_set_workspace(cs3d_batch b, void* dev, size_t bytes) {
   if (!b || !dev || ((uintptr_t)dev & 255)) return CS3D_E_INVAL;
   if (bytes < b->bytes) return CS3D_E_WORKSPACE;
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
   b->ws = dev;
   for (size_t i = 0; i < b->plans.size(); ++i)
     cs3d_set_workspace(b->plans[i], (char*)dev + b->offs[i], cs3d_workspace_bytes(b->plans[i], 1));
+  b->have_ptrs = false;  // the descriptors carry the workspace addresses
+  return CS3D_OK;
+}
+
+static cs3d_status batch_solve_impl(cs3d_batch b, const double* const* f, double* const* u, hipStream_t s) {
+  if (!b || !f || !u) return CS3D_E_INVAL;
+  for (int i = 0; i < b->n; ++i)
+    if (!f[i] || !u[i]) return CS3D_E_INVAL;
+  if (!b->ws) return CS3D_E_WORKSPACE;
+  cs3d_status st;
+  if (!b->ready && (st = batch_prepare(b)) != CS3D_OK) return st;
+  bool changed = !b->have_ptrs;
+  for (int i = 0; i < b->n && !changed; ++i) changed = f[i] != b->cur_f[i] || u[i] != b->cur_u[i];
+  if (changed) {
+    if (b->up_pending && hipEventSynchronize(b->up_ev) != hipSuccess) return CS3D_E_DEVICE;
+    for (int i = 0; i < b->n; ++i) {
+      // the FP64 path: the RHS pass writes F into u, which the inverse x pass overwrites last
+      ProbDev pd = make_pd(b->plans[i], f[i], nullptr, nullptr, u[i], u[i], 1);
+      pd.stats = b->dstats + (size_t)i * kStatsWords;
+      pd.zchunk = b->tune.zchunk;
+      pd.accumulate = 0;
+      b->hP[i] = pd;
+      b->cur_f[i] = f[i];
+      b->cur_u[i] = u[i];
+    }
+    if (hipMemcpyAsync(b->dP, b->hP, b->n * sizeof(ProbDev), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(b->up_ev, s) != hipSuccess)
+      return CS3D_E_DEVICE;
+    b->up_pending = true;
+    b->have_ptrs = true;
+  }
+  if (b->tune.graph) {
+    if (!b->exec && (st = batch_capture(b)) != CS3D_OK) return st;
+    if (hipEventRecord(b->ev[0], s) != hipSuccess || hipGraphLaunch(b->exec, s) != hipSuccess ||
+        hipEventRecord(b->ev[kPasses], s) != hipSuccess)
+      return CS3D_E_DEVICE;
+    b->staged = false;
+  } else {
+    if (hipEventRecord(b->ev[0], s) != hipSuccess || batch_launch(b, s, true) != hipSuccess) return CS3D_E_DEVICE;
+    b->staged = true;
+  }
+  b->last_stream = s;
+  b->timed = true;
   return CS3D_OK;
 }
 
 extern "C" cs3d_status cs3d_batch_solve(cs3d_batch b, const double* const* f, double* const* u, void* s) {
-  if (!b || !f || !u) return CS3D_E_INVAL;
-  if (!b->ws) return CS3D_E_WORKSPACE;
-  for (size_t i = 0; i < b->plans.size(); ++i) {
-    cs3d_status st = cs3d_solve(b->plans[i], 1, f[i], nullptr, nullptr, u[i], s);
-    if (st != CS3D_OK) return st;
+  return batch_solve_impl(b, f, u, (hipStream_t)s);
+}
+
+static cs3d_status batch_sync(cs3d_batch b) {
+  if (b->last_stream && hipStreamSynchronize(b->last_stream) != hipSuccess) return CS3D_E_DEVICE;
+  if (!b->last_stream && hipDeviceSynchronize() != hipSuccess) return CS3D_E_DEVICE;
+  return CS3D_OK;
+}
+
+static cs3d_status batch_timing(cs3d_batch b, cs3d_stats* out) {
+  for (double& v : out->residual_history) v = NAN;
+  if (!b->timed) return CS3D_OK;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, b->ev[0], b->ev[kPasses]) != hipSuccess) return CS3D_E_DEVICE;
+  out->last_solve_ms = ms;
+  if (b->staged) {
+    out->stage_count = kPasses;
+    out->timed_solves = 1;
+    for (int k = 0; k < kPasses; ++k) {
+      if (hipEventElapsedTime(&ms, b->ev[k], b->ev[k + 1]) != hipSuccess) return CS3D_E_DEVICE;
+      out->stage_ms[k] = ms;
+    }
   }
   return CS3D_OK;
 }
 
 extern "C" cs3d_status cs3d_batch_get_stats(cs3d_batch b, cs3d_stats* out) {
   if (!b || !out) return CS3D_E_INVAL;
-  cs3d_stats acc{};
-  acc.min_abs_pivot = INFINITY;
-  cs3d_status worst = CS3D_OK;
-  for (cs3d_plan p : b->plans) {
-    cs3d_stats st{};
-    cs3d_status r = cs3d_get_stats(p, &st);
-    if (r == CS3D_E_DEVICE) return r;
-    if (r != CS3D_OK) worst = r;
-    acc.min_abs_pivot = std::fmin(acc.min_abs_pivot, st.min_abs_pivot);
-    acc.bad_pivots += st.bad_pivots;
+  std::memset(out, 0, sizeof(*out));
+  cs3d_status st = batch_sync(b);
+  if (st != CS3D_OK) return st;
+  std::vector<unsigned long long> h((size_t)b->n * kStatsWords);
+  if (hipMemcpy(h.data(), b->dstats, h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return CS3D_E_DEVICE;
+  double mn = INFINITY;
+  long long bad = 0;
+  for (int i = 0; i < b->n; ++i) {
+    double v;
+    std::memcpy(&v, &h[(size_t)i * kStatsWords], 8);
+    mn = std::fmin(mn, v);
+    bad += (long long)h[(size_t)i * kStatsWords + 1];
   }
-  for (double& v : acc.residual_history) v = NAN;
-  *out = acc;
-  return worst;
+  out->min_abs_pivot = mn;
+  out->bad_pivots = bad;
+  if ((st = batch_timing(b, out)) != CS3D_OK) return st;
+  return bad ? CS3D_E_SINGULAR : CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_batch_member_stats(cs3d_batch b, int i, cs3d_stats* out) {
+  if (!b || !out || i < 0 || i >= b->n) return CS3D_E_INVAL;
+  std::memset(out, 0, sizeof(*out));
+  cs3d_status st = batch_sync(b);
+  if (st != CS3D_OK) return st;
+  unsigned long long h[2];
+  if (hipMemcpy(h, b->dstats + (size_t)i * kStatsWords, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return CS3D_E_DEVICE;
+  std::memcpy(&out->min_abs_pivot, &h[0], 8);
+  out->bad_pivots = (int64_t)h[1];
+  if ((st = batch_timing(b, out)) != CS3D_OK) return st;
+  return h[1] ? CS3D_E_SINGULAR : CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_batch_get_tuning(cs3d_batch b, cs3d_tuning* out) {
+  if (!b || !out) return CS3D_E_INVAL;
+  tuning_out(b->tune, out);
+  return CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_batch_set_tuning(cs3d_batch b, const cs3d_tuning* t) {
+  if (!b || !tuning_ok(t)) return CS3D_E_INVAL;
+  if (b->last_stream && hipStreamSynchronize(b->last_stream) != hipSuccess) return CS3D_E_DEVICE;
+  const bool lists = t->zchunk != b->tune.zchunk || t->order != b->tune.order;
+  b->tune.zchunk = t->zchunk;
+  b->tune.order = t->order;
+  b->tune.graph = t->graph;
+  if (lists) {
+    b->ready = false;
+    b->have_ptrs = false;  // zchunk is in the descriptors
+    batch_drop_graph(b);   // grids and totals are baked into the graph
+  }
+  return CS3D_OK;
+}
+
+extern "C" cs3d_status cs3d_batch_autotune(cs3d_batch b, const double* const* f, double* const* u, void* stream,
+                                           int reps, cs3d_tuning* out_best, double* out_ms) {
+  if (!b || reps < 1) return CS3D_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  cs3d_tuning best;
+  tuning_out(b->tune, &best);
+  cs3d_status st;
+  // per-pass timings of `reps` solves launched pass by pass
+  auto run = [&](const cs3d_tuning& t, double (&stage)[kPasses]) -> cs3d_status {
+    cs3d_tuning u0 = t;
+    u0.graph = 0;
+    cs3d_status r = cs3d_batch_set_tuning(b, &u0);
+    if (r != CS3D_OK) return r;
+    for (double& v : stage) v = 0.0;
+    for (int k = 0; k <= reps; ++k) {
+      if ((r = batch_solve_impl(b, f, u, s)) != CS3D_OK) return r;
+      cs3d_stats S;
+      r = cs3d_batch_get_stats(b, &S);
+      if (r == CS3D_E_DEVICE) return r;
+      if (k > 0)  // the first solve is a warm-up
+        for (int q = 0; q < kPasses; ++q) stage[q] += S.stage_ms[q] / reps;
+    }
+    return CS3D_OK;
+  };
+  double stage[kPasses];
+  // zchunk shapes the RHS pass only
+  double bt = INFINITY;
+  int bz = best.zchunk;
+  for (int z : {16, 32, 64, 128}) {
+    cs3d_tuning t = best;
+    t.zchunk = z;
+    if ((st = run(t, stage)) != CS3D_OK) return st;
+    if (stage[kPassRhs] < bt) {
+      bt = stage[kPassRhs];
+      bz = z;
+    }
+  }
+  best.zchunk = bz;
+  // the member order shapes every pass
+  bt = INFINITY;
+  int bo = best.order;
+  for (int o : {0, 1}) {
+    cs3d_tuning t = best;
+    t.order = o;
+    if ((st = run(t, stage)) != CS3D_OK) return st;
+    double tt = 0.0;
+    for (double v : stage) tt += v;
+    if (tt < bt) {
+      bt = tt;
+      bo = o;
+    }
+  }
+  best.order = bo;
+  best.graph = 1;
+  if ((st = cs3d_batch_set_tuning(b, &best)) != CS3D_OK) return st;
+  // graph replay timing of the final choice
+  if ((st = batch_solve_impl(b, f, u, s)) != CS3D_OK) return st;
+  if (hipEventRecord(b->tev0, s) != hipSuccess) return CS3D_E_DEVICE;
+  for (int k = 0; k < reps; ++k)
+    if ((st = batch_solve_impl(b, f, u, s)) != CS3D_OK) return st;
+  if (hipEventRecord(b->tev1, s) != hipSuccess || hipEventSynchronize(b->tev1) != hipSuccess) return CS3D_E_DEVICE;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, b->tev0, b->tev1) != hipSuccess) return CS3D_E_DEVICE;
+  if (out_best) *out_best = best;
+  if (out_ms) *out_ms = ms / reps;
+  return CS3D_OK;
 }
 
 extern "C" cs3d_status cs3d_batch_destroy(cs3d_batch b) {
-  if (!b) return CS3D_OK;
-  for (cs3d_plan p : b->plans) cs3d_plan_destroy(p);
-  delete b;
+  batch_free(b);
   return CS3D_OK;
 }

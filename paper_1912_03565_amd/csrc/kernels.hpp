@@ -31,6 +31,7 @@ constexpr int kBlockY = 256;  // threads per K2/K3 workgroup
 struct ProbDev {
   int nx, ny, nz;
   int Mx, My;          // N+1 per axis
+  int fx, fy;          // FFT length per axis (N+1 when a power of two in 64..1024), 0 = dense sine sums
   int ldy;             // row length of a y-line in G / C (multiple of 16, >= ny+1)
   int scheme;
   double hx, hy, hz, gamma;
@@ -60,6 +61,7 @@ struct ProbDev {
   double* C;           // [nz][nx][ldy]   c' of the tridiagonal LU
   unsigned long long* stats;  // [0] = bits of min |pivot|, [1] = count of bad pivots
   int accumulate;      // K4: u += result (refinement corrections) instead of u = result
+  int zchunk;          // planes per workgroup of the z-marching passes (K0, residual)
 };
 
 // ---------------------------------------------------------------------------
@@ -116,7 +118,7 @@ __host__ __device__ constexpr int tile_stride(int nx) { return (nx & 1) ? nx + 2
 // K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 512 threads
 // (64 x 8, two y-rows each), marching over kZChunk planes with two planes in flight.
 // ---------------------------------------------------------------------------
-constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;
+constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;  // kZChunk: default planes per workgroup
 constexpr int kSX = kRX + 2 * kRH, kSY = kRY + 2 * kRH;
 
 __device__ __forceinline__ double d4_onesided(const double* c, long long s, bool low) {
@@ -139,14 +141,13 @@ constexpr int kRThreads = 512;
 constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread
 constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
-__global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
-  __shared__ double win[5][kSY * kSX];
+// one 64 x 16 tile (bx, by) over the z-chunk zc of right-hand side r
+__device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int zc, int r,
+                                          double (*win)[kSY * kSX]) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
-  const int nzc = (p.nz + kZChunk - 1) / kZChunk;
-  const int zc = blockIdx.z % nzc, r = blockIdx.z / nzc;
-  const int lb = 1 + zc * kZChunk;
-  const int le = min(p.nz, lb + kZChunk - 1);
+  const int x0 = 1 + bx * kRX, y0 = 1 + by * kRY;
+  const int lb = 1 + zc * p.zchunk;
+  const int le = min(p.nz, lb + p.zchunk - 1);
   const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
   const double* __restrict__ f = p.f + r * p.f_stride;
   const int halo = (p.scheme == kHelm6) ? 2 : 1;
@@ -259,6 +260,12 @@ __global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
   }
 }
 
+__global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
+  __shared__ double win[5][kSY * kSX];
+  const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
+  rhs_block(p, blockIdx.x, blockIdx.y, blockIdx.z % nzc, blockIdx.z / nzc, win);
+}
+
 // ---------------------------------------------------------------------------
 // K1: DST along x of 8 lines of F, transposed store into y-lines.  Persistent:
 // each workgroup walks tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... (8 y-lines
@@ -364,30 +371,40 @@ __device__ __forceinline__ void flush_stats(const ProbDev& p, double minpiv, uns
   }
 }
 
-// waves per line in the y passes: two for the 1024-point FFT, one otherwise
+// waves per line in the y passes (1, or 2 for M >= 512); the default is two for the
+// 1024-point FFT and one otherwise, the autotuner may pick the other one
 template <int MY>
+constexpr int default_wpl() { return MY == 1024 ? 2 : 1; }
+
+template <int MY, int WPL_ = default_wpl<MY>()>
 struct YCfg {
-  static constexpr int WPL = (MY == 1024) ? 2 : 1;
+  static constexpr int WPL = WPL_;
   static constexpr int LANES = 64 * WPL;
   static constexpr int LPB = kBlockY / LANES;  // lines (x-modes) per workgroup
   static constexpr int NS = Tx<MY, WPL>::NS;
   static constexpr int NLD = (MY ? MY : 1024) / LANES;  // line values loaded per lane
 };
 
-template <typename T, int MY>
-__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p) {
-  using C = YCfg<MY>;
-  constexpr int NS = C::NS, WPL = C::WPL;
-  extern __shared__ double smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
+// twiddle tables of a y pass, loaded by the whole block (a barrier follows)
+template <typename T, int MY, int WPL>
+__device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load) {
   const int bufn = line_buf_elems<T, MY>(p.ny);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + C::LPB * bufn);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + YCfg<MY, WPL>::LPB * bufn);
   if constexpr (MY != 0) {
-    load_twiddles<T, MY, WPL>(tab, p.twy);
-    __syncthreads();
+    if (load) load_twiddles<T, MY, WPL>(tab, p.twy);
   }
+  __syncthreads();
+  return tab;
+}
+
+// lines n = g LPB + 1 .. of right-hand side r (tables already in LDS)
+template <typename T, int MY, int WPL>
+__device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r, T* smem, const cx<T>* tab) {
+  using C = YCfg<MY, WPL>;
+  constexpr int NS = C::NS;
+  const int bufn = line_buf_elems<T, MY>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
-  const int n = blockIdx.x * C::LPB + line + 1, r = blockIdx.y;
+  const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
   if constexpr (WPL == 1) {
     if (!active) return;  // no workgroup barrier below for single-wave lines
@@ -458,23 +475,24 @@ __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p) {
   if (active || WPL > 1) flush_stats(p, minpiv, bad);
 }
 
+template <typename T, int MY, int WPL = default_wpl<MY>()>
+__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p) {
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
+  yfwd_block<T, MY, WPL>(p, blockIdx.x, blockIdx.y, smem, tab);
+}
+
 // ---------------------------------------------------------------------------
 // K3: back substitution + inverse DST along y.
 // ---------------------------------------------------------------------------
-template <typename T, int MY>
-__global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
-  using C = YCfg<MY>;
-  constexpr int NS = C::NS, WPL = C::WPL;
-  extern __shared__ double smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
+template <typename T, int MY, int WPL>
+__device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r, T* smem, const cx<T>* tab) {
+  using C = YCfg<MY, WPL>;
+  constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY>(p.ny);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + C::LPB * bufn);
-  if constexpr (MY != 0) {
-    load_twiddles<T, MY, WPL>(tab, p.twy);
-    __syncthreads();
-  }
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
-  const int n = blockIdx.x * C::LPB + line + 1, r = blockIdx.y;
+  const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
   if constexpr (WPL == 1) {
     if (!active) return;
@@ -525,6 +543,14 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
       if (mpos[s] > 0) line_p[mpos[s]] = out[s];
     line_sync<WPL>();
   }
+}
+
+template <typename T, int MY, int WPL = default_wpl<MY>()>
+__global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
+  yback_block<T, MY, WPL>(p, blockIdx.x, blockIdx.y, smem, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,10 +633,10 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
   __shared__ double part[kRThreads / 64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
-  const int nzc = (p.nz + kZChunk - 1) / kZChunk;
+  const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int zc = blockIdx.z % nzc, r = blockIdx.z / nzc;
-  const int lb = 1 + zc * kZChunk;
-  const int le = min(p.nz, lb + kZChunk - 1);
+  const int lb = 1 + zc * p.zchunk;
+  const int le = min(p.nz, lb + p.zchunk - 1);
   const long long plane = (long long)p.nx * p.ny;
   const double* __restrict__ Ur = U + r * p.u_stride;
   long long off[kQLoads];

@@ -55,12 +55,30 @@ class Stats(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("zchunk", ctypes.c_int), ("xpersist", ctypes.c_int), ("ywpl", ctypes.c_int),
+        ("order", ctypes.c_int), ("graph", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for k, _ in cls._fields_:
+            setattr(t, k, int(d[k]))
+        return t
+
+
 EXPORTS = [
     "cs3d_plan_create", "cs3d_plan_destroy", "cs3d_workspace_bytes", "cs3d_set_workspace",
     "cs3d_solve", "cs3d_solve_assembled", "cs3d_residual", "cs3d_get_stats",
     "cs3d_batch_create", "cs3d_batch_workspace_bytes", "cs3d_batch_set_workspace",
     "cs3d_batch_solve", "cs3d_batch_get_stats", "cs3d_batch_destroy", "cs3d_status_str",
-    "cs3d_version", "cs3d_reset_timers",
+    "cs3d_version", "cs3d_reset_timers", "cs3d_get_tuning", "cs3d_set_tuning", "cs3d_autotune",
+    "cs3d_batch_member_stats", "cs3d_batch_get_tuning", "cs3d_batch_set_tuning", "cs3d_batch_autotune",
 ]
 
 
@@ -72,7 +90,7 @@ class CS3DError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1912_03565_amd.build")
+        raise ImportError(f"{LIB_PATH} is missing: build it with python paper_1912_03565_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, sz, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
     sig = {
@@ -91,6 +109,15 @@ def _load():
         "cs3d_batch_solve": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "cs3d_batch_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
         "cs3d_batch_destroy": (i, [vp]),
+        "cs3d_batch_member_stats": (i, [vp, i, ctypes.POINTER(Stats)]),
+        "cs3d_batch_get_tuning": (i, [vp, ctypes.POINTER(Tuning)]),
+        "cs3d_batch_set_tuning": (i, [vp, ctypes.POINTER(Tuning)]),
+        "cs3d_batch_autotune": (i, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, i,
+                                    ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]),
+        "cs3d_get_tuning": (i, [vp, ctypes.POINTER(Tuning)]),
+        "cs3d_set_tuning": (i, [vp, ctypes.POINTER(Tuning)]),
+        "cs3d_autotune": (i, [vp, i, dp, dp, dp, dp, vp, i, ctypes.POINTER(Tuning),
+                              ctypes.POINTER(ctypes.c_double)]),
         "cs3d_status_str": (ctypes.c_char_p, [i]),
         "cs3d_version": (ctypes.c_char_p, []),
     }

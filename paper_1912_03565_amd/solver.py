@@ -46,6 +46,27 @@ def _aligned_workspace(nbytes, device):
     return buf, buf.data_ptr() + off
 
 
+def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
+               weights=None, precision="fp64", refine_steps=2, max_rhs=1):
+    """cs3d_desc and the host arrays it points to (keep them alive during the call)."""
+    keep = []
+    d = N.Desc()
+    d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+    d.hx, d.hy, d.hz = float(hx), float(hy), float(hz)
+    d.scheme = N.SCHEMES[scheme]
+    for field, arr, n in (("k2", k2, nz + 2), ("k2_z", k2_z, nz + 2), ("k2_zz", k2_zz, nz + 2),
+                          ("weights", weights, nz * 12)):
+        a, ptr = _host_array(arr, n, field)
+        keep.append(a)
+        if ptr is not None:
+            setattr(d, field, ptr)
+    d.gamma = float(gamma)
+    d.precision = N.PRECISIONS[precision]
+    d.refine_steps = int(refine_steps)
+    d.max_rhs = int(max_rhs)
+    return d, keep
+
+
 class Plan:
     """A solver plan for one grid, scheme and coefficient set (cs3d_plan_create)."""
 
@@ -54,23 +75,11 @@ class Plan:
                  device="cuda", stream=None):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.scheme = scheme
+        self.precision = precision
         self.max_rhs = int(max_rhs)
         self.device = torch.device(device)
-        keep = []
-        d = N.Desc()
-        d.nx, d.ny, d.nz = self.nx, self.ny, self.nz
-        d.hx, d.hy, d.hz = float(hx), float(hy), float(hz)
-        d.scheme = N.SCHEMES[scheme]
-        for field, arr, n in (("k2", k2, nz + 2), ("k2_z", k2_z, nz + 2), ("k2_zz", k2_zz, nz + 2),
-                              ("weights", weights, nz * 12)):
-            a, p = _host_array(arr, n, field)
-            keep.append(a)
-            if p is not None:
-                setattr(d, field, p)
-        d.gamma = float(gamma)
-        d.precision = N.PRECISIONS[precision]
-        d.refine_steps = int(refine_steps)
-        d.max_rhs = self.max_rhs
+        d, keep = _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2, k2_z, k2_zz, gamma, weights,
+                             precision, refine_steps, max_rhs)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             N.check("cs3d_plan_create",
@@ -162,6 +171,31 @@ class Plan:
     def reset_timers(self):
         N.check("cs3d_reset_timers", N.lib.cs3d_reset_timers(self._plan))
 
+    # launch shapes -------------------------------------------------------
+    def tuning(self):
+        t = N.Tuning()
+        N.check("cs3d_get_tuning", N.lib.cs3d_get_tuning(self._plan, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, tuning):
+        t = N.Tuning.from_dict({**self.tuning(), **tuning})
+        N.check("cs3d_set_tuning", N.lib.cs3d_set_tuning(self._plan, ctypes.byref(t)))
+
+    def autotune(self, f, out=None, reps=2, stream=None):
+        """Time the launch-shape candidates on solves of f (cs3d_autotune) and keep the best;
+        returns (tuning dict, ms per solve)."""
+        nrhs = self._nrhs(f)
+        _check_dev(f, self.closed_shape(nrhs), "f")
+        if out is None:
+            out = torch.empty(self.interior_shape(nrhs), dtype=torch.float64, device=f.device)
+        _check_dev(out, self.interior_shape(nrhs), "out")
+        t, ms = N.Tuning(), ctypes.c_double()
+        N.check("cs3d_autotune",
+                N.lib.cs3d_autotune(self._plan, nrhs, f.data_ptr(), None, None, out.data_ptr(),
+                                    _stream_handle(stream), int(reps), ctypes.byref(t), ctypes.byref(ms)),
+                allow=(N.E_SINGULAR, N.E_NOTCONVERGED))
+        return t.as_dict(), ms.value
+
     def close(self):
         if getattr(self, "_plan", None) and self._plan.value:
             N.lib.cs3d_plan_destroy(self._plan)
@@ -182,3 +216,111 @@ def plan_for_problem(p, precision="fp64", refine_steps=2, max_rhs=None, device="
                 k2_zz=p.k2_zz if p.scheme == "helm6" else None, gamma=p.gamma, weights=weights,
                 precision=precision, refine_steps=refine_steps,
                 max_rhs=max_rhs or p.nrhs, device=device)
+
+
+class Batch:
+    """Many independent problems solved together (cs3d_batch_create): one launch per pass
+    over the work items of all members, replayed from a captured HIP graph.
+
+    members: list of dicts with the keyword arguments of Plan (nx, ny, nz, hx, hy, hz,
+    scheme, k2, k2_z, k2_zz, gamma); every member takes one right-hand side, FP64."""
+
+    def __init__(self, members, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.shapes = [(int(m["nx"]), int(m["ny"]), int(m["nz"])) for m in members]
+        n = len(members)
+        descs = (N.Desc * n)()
+        keep = []
+        for i, m in enumerate(members):
+            d, k = _make_desc(m["nx"], m["ny"], m["nz"], m["hx"], m["hy"], m["hz"], m["scheme"],
+                              m.get("k2"), m.get("k2_z"), m.get("k2_zz"), m.get("gamma", 0.0),
+                              None, "fp64", 0, 1)
+            descs[i] = d
+            keep.append(k)
+        self._b = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            N.check("cs3d_batch_create",
+                    N.lib.cs3d_batch_create(n, descs, _stream_handle(stream), ctypes.byref(self._b)))
+            self.ws_bytes = N.lib.cs3d_batch_workspace_bytes(self._b)
+            self._ws, ptr = _aligned_workspace(self.ws_bytes, self.device)
+            N.check("cs3d_batch_set_workspace", N.lib.cs3d_batch_set_workspace(self._b, ptr, self.ws_bytes))
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def _ptrs(self, fs, us):
+        n = len(self.shapes)
+        if len(fs) != n or len(us) != n:
+            raise ValueError(f"expected {n} right-hand sides and {n} outputs")
+        for i, ((nx, ny, nz), f, u) in enumerate(zip(self.shapes, fs, us)):
+            _check_dev(f, (nz + 2, ny + 2, nx + 2), f"f[{i}]")
+            _check_dev(u, (nz, ny, nx), f"u[{i}]")
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        return fp, up
+
+    def outputs(self):
+        return [torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device) for nx, ny, nz in self.shapes]
+
+    def solve(self, fs, us=None, stream=None):
+        """fs[i]: closed-grid f of member i, shape (nz+2, ny+2, nx+2); returns the interior solutions."""
+        if us is None:
+            us = self.outputs()
+        fp, up = self._ptrs(fs, us)
+        N.check("cs3d_batch_solve", N.lib.cs3d_batch_solve(self._b, fp, up, _stream_handle(stream)))
+        return us
+
+    def _stats_dict(self, s, st):
+        return {"status": st, "min_abs_pivot": s.min_abs_pivot, "bad_pivots": int(s.bad_pivots),
+                "last_solve_ms": s.last_solve_ms, "stage_ms": [s.stage_ms[k] for k in range(s.stage_count)]}
+
+    def stats(self):
+        s = N.Stats()
+        st = N.check("cs3d_batch_get_stats", N.lib.cs3d_batch_get_stats(self._b, ctypes.byref(s)),
+                     allow=(N.E_SINGULAR,))
+        return self._stats_dict(s, st)
+
+    def member_stats(self, i):
+        s = N.Stats()
+        st = N.check("cs3d_batch_member_stats", N.lib.cs3d_batch_member_stats(self._b, int(i), ctypes.byref(s)),
+                     allow=(N.E_SINGULAR,))
+        return self._stats_dict(s, st)
+
+    def tuning(self):
+        t = N.Tuning()
+        N.check("cs3d_batch_get_tuning", N.lib.cs3d_batch_get_tuning(self._b, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, tuning):
+        t = N.Tuning.from_dict({**self.tuning(), **tuning})
+        N.check("cs3d_batch_set_tuning", N.lib.cs3d_batch_set_tuning(self._b, ctypes.byref(t)))
+
+    def autotune(self, fs, us=None, reps=2, stream=None):
+        if us is None:
+            us = self.outputs()
+        fp, up = self._ptrs(fs, us)
+        t, ms = N.Tuning(), ctypes.c_double()
+        N.check("cs3d_batch_autotune",
+                N.lib.cs3d_batch_autotune(self._b, fp, up, _stream_handle(stream), int(reps), ctypes.byref(t),
+                                          ctypes.byref(ms)),
+                allow=(N.E_SINGULAR,))
+        return t.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            N.lib.cs3d_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_member(p):
+    """Batch member keywords of a one-right-hand-side workloads.Problem."""
+    return dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, hz=p.hz, scheme=p.scheme, k2=p.k2,
+                k2_z=p.k2_z if p.scheme == "helm6" else None, k2_zz=p.k2_zz if p.scheme == "helm6" else None,
+                gamma=p.gamma)

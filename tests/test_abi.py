@@ -92,3 +92,54 @@ def test_null_arguments_are_rejected(N):
     assert N.lib.cs3d_plan_destroy(None) == N.OK
     assert N.lib.cs3d_batch_destroy(None) == N.OK
     assert N.lib.cs3d_get_stats(None, None) == N.E_INVAL
+    assert N.lib.cs3d_get_tuning(None, None) == N.E_INVAL
+    assert N.lib.cs3d_set_tuning(None, None) == N.E_INVAL
+    assert N.lib.cs3d_autotune(None, 1, None, None, None, None, None, 1, None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_create(0, None, None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_solve(None, None, None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_get_stats(None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_member_stats(None, 0, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_get_tuning(None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_set_tuning(None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_autotune(None, None, None, None, 1, None, None) == N.E_INVAL
+    assert N.lib.cs3d_batch_workspace_bytes(None) == 0
+
+
+@pytest.mark.parametrize("case", ["weights", "mixed", "bad_member"])
+def test_batch_create_rejects_members(N, case):
+    descs = (N.Desc * 2)()
+    keep = []
+    for i in range(2):
+        d = _desc(N, n=(63, 63, 63))
+        keep.append(d._keep)
+        descs[i] = d
+    if case == "weights":
+        descs[1].scheme = N.SCHEMES["weights"]
+        want = N.E_INVAL
+    elif case == "mixed":
+        descs[0].precision = N.PRECISIONS["mixed"]
+        want = N.E_UNSUPPORTED
+    else:
+        descs[1].nx = 0
+        want = N.E_INVAL
+    b = ctypes.c_void_p()
+    assert N.lib.cs3d_batch_create(2, descs, None, ctypes.byref(b)) == want
+    assert not b.value
+
+
+def test_tuning_cache_store_and_load(tmp_path, monkeypatch):
+    from paper_1912_03565_amd import tuning
+    path = str(tmp_path / "sub" / "tune.json")
+    monkeypatch.setenv("CS3D_TUNE_CACHE", path)
+    assert tuning.cache_path() == path
+    assert tuning.load() == {}
+    tuning.store("dev|plan|63x63x63|helm6|fp64|rhs1", {"tuning": {"zchunk": 16}, "ms": 1.5})
+    tuning.store("dev|batch|n64|abc", {"tuning": {"zchunk": 64}, "ms": 9.0})
+    data = tuning.load()
+    assert data["dev|plan|63x63x63|helm6|fp64|rhs1"]["tuning"]["zchunk"] == 16
+    assert len(data) == 2
+    with open(path, "w") as fh:
+        fh.write("{not json")
+    assert tuning.load() == {}  # a damaged cache is ignored, not fatal
+    monkeypatch.setenv("CS3D_AUTOTUNE", "0")
+    assert not tuning.enabled()
