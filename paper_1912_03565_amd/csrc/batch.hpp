@@ -4,7 +4,8 @@
 // side each) is solved by one launch per pass.  Every pass has a work list: the k-th
 // member of the pass's order, perm[k], owns items start[k] .. start[k+1]-1 (tiles of
 // the x passes and of the z-marching RHS pass, line groups of the y passes).
-// Workgroups are resident and walk the items blockIdx.x, blockIdx.x + gridDim.x, ...;
+// Workgroups are resident and walk the items t0, t0 + gridDim.x, ... (t0 the
+// XCD-ordered index of the workgroup, so each XCD takes neighbouring items);
 // each item finds its member by binary search in start[] and runs the same per-item
 // code as a single solve, dispatched on the member's line-transform size.  With the
 // members ordered by decreasing cost per item, the long items are taken first.
@@ -77,7 +78,7 @@ __device__ __forceinline__ void dispatch_m(int M, Fn&& fn) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
   __shared__ double win[5][kSY * kSX];
-  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+  for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev& p = b.P[b.perm[k]];
     const int t = item - b.start[k];
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
   cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
   T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
   int curM = -1;
-  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+  for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev& p = b.P[b.perm[k]];
     const int t = item - b.start[k];
@@ -189,7 +190,7 @@ __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
   cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
   T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
   int curM = -1;
-  for (int item = blockIdx.x; item < b.total; item += gridDim.x) {
+  for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev& p = b.P[b.perm[k]];
     const int g = item - b.start[k];

@@ -115,6 +115,34 @@ __host__ __device__ constexpr int tw_bytes() {
 __host__ __device__ constexpr int tile_stride(int nx) { return (nx & 1) ? nx + 2 : nx + 1; }
 
 // ---------------------------------------------------------------------------
+// Hide a value from loop-invariant code motion (an empty asm statement that claims to
+// change it): per-thread offsets derived from it are then recomputed where used instead
+// of being hoisted out of a persistent loop as one live register pair per access.
+template <typename V>
+__device__ __forceinline__ V opaque(V v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware work order.  The 8 XCDs of the chip each have their own L2, and
+// workgroups are handed to them round-robin by linear index.  xcd_order maps the
+// linear index L of a grid of n workgroups to a work index so that every XCD receives
+// one contiguous range of work indices: neighbouring tiles, which share cache lines
+// (x passes) or stencil halos (z-marching passes), then meet in the same L2.
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_order(int L, int n) {
+  const int q = n / kXcds;
+  return L < q * kXcds ? (L % kXcds) * q + L / kXcds : L;
+}
+
+__device__ __forceinline__ int linear_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+// ---------------------------------------------------------------------------
 // K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 512 threads
 // (64 x 8, two y-rows each), marching over kZChunk planes with two planes in flight.
 // ---------------------------------------------------------------------------
@@ -260,20 +288,24 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
   }
 }
 
+// grid: (x tiles) x (y tiles) x (z chunks x right-hand sides), taken in XCD order
 __global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
   __shared__ double win[5][kSY * kSX];
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
-  rhs_block(p, blockIdx.x, blockIdx.y, blockIdx.z % nzc, blockIdx.z / nzc, win);
+  const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
+  const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
+  rhs_block(p, bx, by, bz % nzc, bz / nzc, win);
 }
 
 // ---------------------------------------------------------------------------
 // K1: DST along x of 8 lines of F, transposed store into y-lines.  Persistent:
-// each workgroup walks tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... (8 y-lines
+// each workgroup walks tiles t = t0, t0 + gridDim.x, ... (t0 its XCD-ordered index; 8 y-lines
 // of one plane of one right-hand side each) and loads the rows of its next tile
 // into registers while it transforms the current one.
 // LDS: 8 line buffers (the transpose tile overlays them) + twiddle table.
 // ---------------------------------------------------------------------------
 constexpr int kNV = 16;  // ceil(1023/64): row values per lane
+constexpr int kXRows = 64 * kTileJ / kTileJ;  // tile rows one pass of an x-pass workgroup covers
 
 struct XTile {
   int jt, l, r, j;
@@ -305,14 +337,13 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   double pre[kNV];
   auto fetch = [&](int t) {
     const XTile x = decode_xtile(p, t, w);
-    const double* Fr = p.F + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
+    const int ln = opaque(lane);
+    const double* Fr =
+        p.F + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1)) + ln;
 #pragma unroll
-    for (int k = 0; k < kNV; ++k) {
-      const int i = 1 + lane + 64 * k;
-      pre[k] = (x.active && i <= p.nx) ? Fr[i - 1] : 0.0;
-    }
+    for (int k = 0; k < kNV; ++k) pre[k] = (x.active && ln + 64 * k < p.nx) ? Fr[64 * k] : 0.0;
   };
-  int t = blockIdx.x;
+  int t = xcd_order(blockIdx.x, gridDim.x);
   if (t < ntiles) fetch(t);
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
@@ -577,28 +608,32 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
   T pre[NT];
+  // thread (n0, jj) moves rows n0, n0 + 64, ... of column jj of the tile; the offsets
+  // are rebuilt per tile from an opaque thread index (kept live across the tile loop,
+  // one 64-bit offset per row would exhaust the registers)
   auto fetch = [&](int t) {
     const XTile x = decode_xtile(p, t, 0);
+    const int tid = opaque((int)threadIdx.x);
+    const int n0 = tid / kTileJ, jj = tid % kTileJ;
     const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
-                 x.jt * kTileJ;
+                 x.jt * kTileJ + (long long)n0 * p.ldy + jj;
+    const long long step = (long long)kXRows * p.ldy;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const int idx = threadIdx.x + 64 * kTileJ * k;
-      const int n0 = idx / kTileJ, jj = idx % kTileJ;
-      pre[k] = (n0 < p.nx) ? G[(long long)n0 * p.ldy + jj] : (T)0;
-    }
+    for (int k = 0; k < NT; ++k) pre[k] = (n0 + kXRows * k < p.nx) ? G[k * step] : (T)0;
   };
-  int t = blockIdx.x;
+  int t = xcd_order(blockIdx.x, gridDim.x);
   if (kInvPrefetch && t < ntiles) fetch(t);
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
     if (!kInvPrefetch) fetch(t);
     __syncthreads();  // the previous transform is done with the LDS
+    {
+      const int tid = opaque((int)threadIdx.x);
+      const int n0 = tid / kTileJ, jj = tid % kTileJ;
+      T* row = smem + jj * ts + n0 + 1;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const int idx = threadIdx.x + 64 * kTileJ * k;
-      const int n0 = idx / kTileJ, jj = idx % kTileJ;
-      if (n0 < p.nx) smem[jj * ts + n0 + 1] = pre[k];
+      for (int k = 0; k < NT; ++k)
+        if (n0 + kXRows * k < p.nx) row[kXRows * k] = pre[k];
     }
     __syncthreads();  // also publishes the twiddle table on the first pass
     if (kInvPrefetch && t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
@@ -632,9 +667,11 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
   __shared__ double win[3][kQX * kQY];
   __shared__ double part[kRThreads / 64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int x0 = 1 + blockIdx.x * kRX, y0 = 1 + blockIdx.y * kRY;
+  const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
+  const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
+  const int x0 = 1 + bx * kRX, y0 = 1 + by * kRY;
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
-  const int zc = blockIdx.z % nzc, r = blockIdx.z / nzc;
+  const int zc = bz % nzc, r = bz / nzc;
   const int lb = 1 + zc * p.zchunk;
   const int le = min(p.nz, lb + p.zchunk - 1);
   const long long plane = (long long)p.nx * p.ny;
