@@ -96,13 +96,17 @@ def cpu_baseline(p_dev, planes):
                       f"columns; {t:.1f} s on {threads} host threads"}
 
 
-def time_path(cs3d, p, nrhs, precision, steps, warmup, dev):
+def time_path(cs3d, p, nrhs, precision, steps, warmup, dev, autotune=True):
     """Warm up, then time `steps` solves with HIP events; returns (u, ms per step, stats)."""
     import torch
 
     plan = cs3d.plan_for_problem(p, precision=precision, refine_steps=2, max_rhs=nrhs, device=dev)
     u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
-    log(f"[bench] {precision}: plan ready, workspace {plan.ws_bytes / 2**30:.2f} GiB; warmup {warmup}")
+    log(f"[bench] {precision}: plan ready, workspace {plan.ws_bytes / 2**30:.2f} GiB")
+    if autotune:
+        tuning, tms = plan.autotune(p.f, out=u, reps=1)
+        log(f"[bench] {precision}: autotuned {tuning} ({tms:.3f} ms)")
+    log(f"[bench] {precision}: warmup {warmup}")
     for _ in range(warmup):
         plan.solve(p.f, out=u)
     torch.cuda.synchronize()
@@ -117,6 +121,7 @@ def time_path(cs3d, p, nrhs, precision, steps, warmup, dev):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     st = plan.stats()
+    st["tuning"] = plan.tuning()
     log(f"[bench] {precision}: {ms:.3f} ms/step; stages {['%.3f' % x for x in st['stage_ms']]}")
     plan.close()
     del plan
@@ -184,6 +189,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="after the timed steps, copy 2 GiB once with a plain device copy "
                          "(the reference for scaling HBM byte counters)")
@@ -204,13 +210,14 @@ def main():
     torch.cuda.synchronize()
     unknowns = nrhs * n ** 3
 
-    u64, ms64, st64 = time_path(cs3d, p, nrhs, "fp64", args.steps, args.warmup, dev)
+    tune = not args.no_autotune
+    u64, ms64, st64 = time_path(cs3d, p, nrhs, "fp64", args.steps, args.warmup, dev, tune)
     paths = {"fp64": {"ms_per_step": round(ms64, 4), "value": round(unknowns / (ms64 / 1e3), 1),
                       "stage_ms": [round(x, 4) for x in st64["stage_ms"]],
-                      "min_abs_pivot": st64["min_abs_pivot"]}}
+                      "min_abs_pivot": st64["min_abs_pivot"], "tuning": st64["tuning"]}}
     best = ("fp64", ms64, st64)
     if not args.no_mixed:
-        umx, msmx, stmx = time_path(cs3d, p, nrhs, "mixed", args.steps, args.warmup, dev)
+        umx, msmx, stmx = time_path(cs3d, p, nrhs, "mixed", args.steps, args.warmup, dev, tune)
         diff = [float(torch.linalg.vector_norm(umx[r] - u64[r]) / torch.linalg.vector_norm(u64[r]))
                 for r in range(nrhs)]
         del umx
@@ -220,7 +227,7 @@ def main():
                           "stage_ms": [round(x, 4) for x in stmx["stage_ms"]],
                           "refine_steps": stmx["refine_done"],
                           "residual_history": [x for x in stmx["residual_history"][: stmx["refine_done"] + 1]],
-                          "rel_err_vs_fp64_gpu": max(diff), "meets_1e-10": ok,
+                          "rel_err_vs_fp64_gpu": max(diff), "meets_1e-10": ok, "tuning": stmx["tuning"],
                           "speedup_vs_fp64": round(ms64 / msmx, 4)}
         log(f"[bench] mixed: rel diff vs fp64 {max(diff):.3e}, residuals {paths['mixed']['residual_history']}")
         if ok and msmx < ms64:

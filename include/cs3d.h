@@ -157,9 +157,9 @@ cs3d_status cs3d_reset_timers(cs3d_plan plan);
 
 /* Launch-shape choices.  Each has a default that needs no tuning; cs3d_autotune and
  * cs3d_batch_autotune time the candidates on the caller's data and keep the fastest.
- * zchunk, xpersist, order and graph do not change the arithmetic (results are bitwise the
- * same for every value); ywpl selects another radix split of the y-line FFT, which changes
- * the rounding of the transform only. */
+ * zchunk, xpersist, yrhs, order and graph do not change the arithmetic (results are bitwise
+ * the same for every value); ywpl selects another radix split of the y-line FFT, which
+ * changes the rounding of the transform only. */
 typedef struct {
   int zchunk;    /* z-planes per workgroup of the z-marching passes (RHS operator and, on the
                     mixed path, the FP64 residual): 8..512, default 32 */
@@ -171,6 +171,9 @@ typedef struct {
                     pass, so the longest items start first (default); 0 = order given */
   int graph;     /* batches: 1 = the passes of a solve are captured once into a HIP graph and
                     replayed (default); 0 = launched one by one, with per-pass timing */
+  int yrhs;      /* y passes of a plan: right-hand sides per workgroup, 1, 2 or 4 (default 1).
+                    Their tridiagonal systems share the modal eigenvalues, the pivots and
+                    each read of c'; transform sizes whose lanes hold 16 modes use 1. */
 } cs3d_tuning;
 
 /* Current launch-shape choices of a plan.  Errors: E_INVAL (NULL argument). */
@@ -229,8 +232,9 @@ cs3d_status cs3d_batch_get_stats(cs3d_batch batch, cs3d_stats* out_stats);
  * timing fields are those of the batch).  Errors: E_INVAL (index out of range). */
 cs3d_status cs3d_batch_member_stats(cs3d_batch batch, int i, cs3d_stats* out_stats);
 
-/* Launch-shape choices of a batch (zchunk, order, graph; xpersist and ywpl are ignored:
- * batch passes are always resident and use the default waves per line).  Setting them
+/* Launch-shape choices of a batch (zchunk, order, graph; xpersist, ywpl and yrhs are
+ * ignored: batch passes are always resident, use the default waves per line and carry the
+ * one right-hand side of each member).  Setting them
  * rebuilds the work lists and drops the captured graph.
  * Errors: E_INVAL (NULL argument or a field out of range), E_DEVICE. */
 cs3d_status cs3d_batch_get_tuning(cs3d_batch batch, cs3d_tuning* out);

@@ -205,8 +205,8 @@ __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
     }
     dispatch_m<MAXM, DENSE>(p.fy, [&](auto mc) {
       constexpr int MM = decltype(mc)::value;
-      if constexpr (FWD) yfwd_block<T, MM, default_wpl<MM>()>(p, g, 0, lines, tab);
-      else yback_block<T, MM, default_wpl<MM>()>(p, g, 0, lines, tab);
+      if constexpr (FWD) yfwd_block<T, MM, default_wpl<MM>(), 1>(p, g, 0, 1, lines, tab);
+      else yback_block<T, MM, default_wpl<MM>(), 1>(p, g, 0, 1, lines, tab);
     });
   }
 }

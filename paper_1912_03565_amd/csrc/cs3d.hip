@@ -52,6 +52,7 @@ struct Tuning {
   int ywpl = 2;          // waves per y-line where the FFT allows two (M >= 512)
   int order = 1;         // batches: members by decreasing cost per item
   int graph = 1;         // batches: captured graph replay
+  int yrhs = 1;          // right-hand sides per y-pass workgroup (1, 2 or 4)
 };
 
 struct cs3d_plan_s {
@@ -426,16 +427,51 @@ static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
   return launch(k_inv_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
+// grid: (line groups, groups of NR right-hand sides)
+template <int MY, int WPL, int NR>
+static dim3 y_grid(const cs3d_plan p, int nrhs) {
+  using C = YCfg<MY, WPL>;
+  return dim3((p->d.nx + C::LPB - 1) / C::LPB, (nrhs + NR - 1) / NR);
+}
+
+// right-hand sides per y-pass workgroup: the tuned choice (1, 2 or 4), at most what the
+// register budget of the transform size allows
+template <typename T, int MY, int WPL, int NR>
+static hipError_t run_y_fwd_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  return launch(k_fwd_y<T, MY, WPL, NR>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY), lds_bytes_y_t<T, MY, WPL>(p),
+                s, pd, nrhs);
+}
+
+template <typename T, int MY, int WPL, int NR>
+static hipError_t run_y_back_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  return launch(k_back_y<T, MY, WPL, NR>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY), lds_bytes_y_t<T, MY, WPL>(p),
+                s, pd, nrhs);
+}
+
+static int y_rhs(const cs3d_plan p, int nrhs, int nrmax) {
+  int nr = p->tune.yrhs < nrmax ? p->tune.yrhs : nrmax;
+  while (nr > 1 && nr / 2 >= nrhs) nr /= 2;  // no wider than the solve
+  return nr;
+}
+
 template <typename T, int MY, int WPL>
 static hipError_t run_y_fwd_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + YCfg<MY, WPL>::LPB - 1) / YCfg<MY, WPL>::LPB, nrhs), block(kBlockY);
-  return launch(k_fwd_y<T, MY, WPL>, grid, block, lds_bytes_y_t<T, MY, WPL>(p), s, pd);
+  if constexpr (YCfg<MY, WPL>::NRMAX >= 4) {
+    const int nr = y_rhs(p, nrhs, 4);
+    if (nr == 4) return run_y_fwd_n<T, MY, WPL, 4>(p, pd, nrhs, s);
+    if (nr == 2) return run_y_fwd_n<T, MY, WPL, 2>(p, pd, nrhs, s);
+  }
+  return run_y_fwd_n<T, MY, WPL, 1>(p, pd, nrhs, s);
 }
 
 template <typename T, int MY, int WPL>
 static hipError_t run_y_back_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  dim3 grid((p->d.nx + YCfg<MY, WPL>::LPB - 1) / YCfg<MY, WPL>::LPB, nrhs), block(kBlockY);
-  return launch(k_back_y<T, MY, WPL>, grid, block, lds_bytes_y_t<T, MY, WPL>(p), s, pd);
+  if constexpr (YCfg<MY, WPL>::NRMAX >= 4) {
+    const int nr = y_rhs(p, nrhs, 4);
+    if (nr == 4) return run_y_back_n<T, MY, WPL, 4>(p, pd, nrhs, s);
+    if (nr == 2) return run_y_back_n<T, MY, WPL, 2>(p, pd, nrhs, s);
+  }
+  return run_y_back_n<T, MY, WPL, 1>(p, pd, nrhs, s);
 }
 
 // waves per y-line: the tuned choice where two are possible (M >= 512), else one
@@ -746,7 +782,8 @@ extern "C" const char* cs3d_version(void) { return "cs3d 0.1 (gfx950)"; }
 // ---------------------------------------------------------------------------
 static bool tuning_ok(const cs3d_tuning* t) {
   return t && t->zchunk >= 8 && t->zchunk <= 512 && (t->xpersist == 0 || t->xpersist == 1) &&
-         (t->ywpl == 1 || t->ywpl == 2) && (t->order == 0 || t->order == 1) && (t->graph == 0 || t->graph == 1);
+         (t->ywpl == 1 || t->ywpl == 2) && (t->order == 0 || t->order == 1) && (t->graph == 0 || t->graph == 1) &&
+         (t->yrhs == 1 || t->yrhs == 2 || t->yrhs == 4);
 }
 
 static void tuning_out(const Tuning& t, cs3d_tuning* o) {
@@ -755,6 +792,7 @@ static void tuning_out(const Tuning& t, cs3d_tuning* o) {
   o->ywpl = t.ywpl;
   o->order = t.order;
   o->graph = t.graph;
+  o->yrhs = t.yrhs;
 }
 
 extern "C" cs3d_status cs3d_get_tuning(cs3d_plan p, cs3d_tuning* out) {
@@ -768,6 +806,7 @@ extern "C" cs3d_status cs3d_set_tuning(cs3d_plan p, const cs3d_tuning* t) {
   p->tune.zchunk = t->zchunk;
   p->tune.xpersist = t->xpersist;
   p->tune.ywpl = t->ywpl;
+  p->tune.yrhs = t->yrhs;
   return CS3D_OK;
 }
 
@@ -803,6 +842,7 @@ extern "C" cs3d_status cs3d_autotune(cs3d_plan p, int nrhs, const double* f, con
   axes.push_back({&Tuning::zchunk, {16, 32, 64, 128}, {0, 5}});
   axes.push_back({&Tuning::xpersist, {0, 1}, {1, 4}});
   if (p->fy >= 512) axes.push_back({&Tuning::ywpl, {1, 2}, {2, 3}});
+  if (nrhs > 1) axes.push_back({&Tuning::yrhs, {1, 2, 4}, {2, 3}});
   for (const Axis& a : axes) {
     double best_t = INFINITY;
     int best_v = best.*(a.field);

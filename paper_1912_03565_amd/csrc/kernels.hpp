@@ -414,6 +414,10 @@ struct YCfg {
   static constexpr int LPB = kBlockY / LANES;  // lines (x-modes) per workgroup
   static constexpr int NS = Tx<MY, WPL>::NS;
   static constexpr int NLD = (MY ? MY : 1024) / LANES;  // line values loaded per lane
+  // most right-hand sides one workgroup carries: their tridiagonal systems share the
+  // eigenvalues and pivots (formed once per plane and mode) and c' (read once in the
+  // back pass); one where a lane holds 16 modes (register budget)
+  static constexpr int NRMAX = NS <= 8 ? 4 : 1;
 };
 
 // twiddle tables of a y pass, loaded by the whole block (a barrier follows)
@@ -428,9 +432,14 @@ __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load)
   return tab;
 }
 
-// lines n = g LPB + 1 .. of right-hand side r (tables already in LDS)
-template <typename T, int MY, int WPL>
-__device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r, T* smem, const cx<T>* tab) {
+// Lines n = g LPB + 1 .. of right-hand sides r0 .. r0 + nr - 1 (nr <= NR; tables already
+// in LDS).  Per plane l the lines of the nr right-hand sides are transformed one after
+// the other through the same line buffer; the modal eigenvalues, the pivot and c' of
+// every mode are formed with the first of them and applied to all (the LU of Section
+// 3.6 does not depend on the right-hand side).  The workgroup of r0 = 0 stores c' and
+// records the pivots.
+template <typename T, int MY, int WPL, int NR>
+__device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY>(p.ny);
@@ -442,83 +451,98 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r, T* sm
   }
   T* buf = smem + line * bufn;
   const double ctn = active ? p.ctx[n - 1] : 0.0;
-  double cp[NS], dp[NS];
+  double cp[NS], dp[NR][NS], lmv[NS], inv[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     cp[s] = 0.0;
-    dp[s] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dp[r][s] = 0.0;
   }
   double minpiv = 1.0e308;
   unsigned bad = 0;
-  T* Gr = reinterpret_cast<T*>(p.G) + r * p.G_stride;
-  const bool write_c = (r == 0);
+  const bool lead = (r0 == 0);  // stores c' and records the pivots
   const long long lstride = (long long)p.nx * p.ldy;
   const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
-  // prefetch of the first line
+  T* G0 = reinterpret_cast<T*>(p.G) + r0 * p.G_stride;
+  // prefetch of the line of the next (plane, right-hand side) pair
   T pre[C::NLD];
+  auto fetch = [&](int l, int r) {
+    const T* src = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase + opaque(tl);
 #pragma unroll
-  for (int s = 0; s < C::NLD; ++s) {
-    const int e = tl + C::LANES * s;
-    pre[s] = (active && e <= p.ny) ? Gr[nbase + e] : (T)0;
-  }
+    for (int s = 0; s < C::NLD; ++s) pre[s] = (active && tl + C::LANES * s <= p.ny) ? src[C::LANES * s] : (T)0;
+  };
+  fetch(1, 0);
   for (int l = 1; l <= p.nz; ++l) {
-    T* line_p = Gr + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
-    for (int s = 0; s < C::NLD; ++s) {
-      const int e = tl + C::LANES * s;
-      if (e <= p.ny) buf[lp(e)] = pre[s];
-    }
-    line_sync<WPL>();
-    if (l < p.nz) {
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nr) break;
+      T* line_p = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
       for (int s = 0; s < C::NLD; ++s) {
         const int e = tl + C::LANES * s;
-        pre[s] = (active && e <= p.ny) ? line_p[lstride + e] : (T)0;
+        if (e <= p.ny) buf[lp(e)] = pre[s];
       }
-    }
-    T out[NS];
-    line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
-    // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
-    const double* Ll = p.LC + (l - 1) * 12;
-    const double bm = Ll[0] + ctn * Ll[1], am = Ll[2] + Ll[3] * ctn;
-    const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
-    const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
-    double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
-    if (active) {
+      line_sync<WPL>();
+      if (r + 1 < nr) fetch(l, r + 1);
+      else if (l < p.nz) fetch(l + 1, 0);
+      T out[NS];
+      line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      if (r == 0) {
+        // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
+        const double* Ll = p.LC + (l - 1) * 12;
+        const double bm = Ll[0] + ctn * Ll[1], am = Ll[2] + Ll[3] * ctn;
+        const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
+        const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
+        double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
+        if (active) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int m = line_mode<MY, WPL>(tl, s, p.ny);
-        if (m > 0) {
-          const double sm = p.cty[m - 1];
-          const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
-          const double piv = l0 - lm * cp[s];
-          record_pivot(piv, minpiv, bad);
-          const double inv = 1.0 / piv;
-          cp[s] = lpv * inv;
-          dp[s] = ((double)out[s] - lm * dp[s]) * inv;
-          line_p[m] = (T)dp[s];
-          if (write_c) Cl[m] = cp[s];
+          for (int s = 0; s < NS; ++s) {
+            const int m = line_mode<MY, WPL>(tl, s, p.ny);
+            if (m > 0) {
+              const double sm = p.cty[m - 1];
+              const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+              const double piv = l0 - lm * cp[s];
+              if (lead) record_pivot(piv, minpiv, bad);
+              inv[s] = 1.0 / piv;
+              lmv[s] = lm;
+              cp[s] = lpv * inv[s];
+              if (lead) Cl[m] = cp[s];
+            }
+          }
         }
       }
+      if (active) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int m = line_mode<MY, WPL>(tl, s, p.ny);
+          if (m > 0) {
+            dp[r][s] = ((double)out[s] - lmv[s] * dp[r][s]) * inv[s];
+            line_p[m] = (T)dp[r][s];
+          }
+        }
+      }
+      line_sync<WPL>();
     }
-    line_sync<WPL>();
   }
-  if (active || WPL > 1) flush_stats(p, minpiv, bad);
+  if (lead && (active || WPL > 1)) flush_stats(p, minpiv, bad);
 }
 
-template <typename T, int MY, int WPL = default_wpl<MY>()>
-__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p) {
+// grid: (line groups, groups of NR right-hand sides)
+template <typename T, int MY, int WPL, int NR>
+__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
-  yfwd_block<T, MY, WPL>(p, blockIdx.x, blockIdx.y, smem, tab);
+  const int r0 = blockIdx.y * NR;
+  yfwd_block<T, MY, WPL, NR>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
-// K3: back substitution + inverse DST along y.
+// K3: back substitution + inverse DST along y, the right-hand sides of a workgroup
+// sharing each read of c'.
 // ---------------------------------------------------------------------------
-template <typename T, int MY, int WPL>
-__device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r, T* smem, const cx<T>* tab) {
+template <typename T, int MY, int WPL, int NR>
+__device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY>(p.ny);
@@ -529,59 +553,71 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r, T* s
     if (!active) return;
   }
   T* buf = smem + line * bufn;
-  double Wn[NS];
+  double Wn[NR][NS];
   int mpos[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     mpos[s] = active ? line_mode<MY, WPL>(tl, s, p.ny) : -1;
-    Wn[s] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) Wn[r][s] = 0.0;
   }
-  T* Gr = reinterpret_cast<T*>(p.G) + r * p.G_stride;
+  T* G0 = reinterpret_cast<T*>(p.G) + r0 * p.G_stride;
   const long long lstride = (long long)p.nx * p.ldy;
   const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
-  // prefetch d' and c' of the last plane
+  // prefetch: d' of the next (plane, right-hand side) pair, c' of the next plane
   T pd[NS];
-  double pc[NS];
+  double pc[NS], pcn[NS];
+  auto fetch_d = [&](int l, int r) {
+    const T* src = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const long long off = (long long)(p.nz - 1) * lstride + nbase + mpos[s];
-    pd[s] = mpos[s] > 0 ? Gr[off] : (T)0;
-    pc[s] = mpos[s] > 0 ? p.C[off] : 0.0;
-  }
+    for (int s = 0; s < NS; ++s) pd[s] = mpos[s] > 0 ? src[mpos[s]] : (T)0;
+  };
+  auto fetch_c = [&](int l, double(&dst)[NS]) {
+    const double* src = p.C + (long long)(l - 1) * lstride + nbase;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dst[s] = mpos[s] > 0 ? src[mpos[s]] : 0.0;
+  };
+  fetch_d(p.nz, 0);
+  fetch_c(p.nz, pc);
   for (int l = p.nz; l >= 1; --l) {
-    T* line_p = Gr + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (mpos[s] > 0) {
-        Wn[s] = (double)pd[s] - pc[s] * Wn[s];
-        buf[lp(mpos[s])] = (T)Wn[s];
-      }
-    }
-    if (tl == 0) buf[lp(0)] = (T)0;
-    line_sync<WPL>();
-    if (l > 1) {
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nr) break;
+      T* line_p = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const long long off = (long long)(l - 2) * lstride + nbase + mpos[s];
-        pd[s] = mpos[s] > 0 ? Gr[off] : (T)0;
-        pc[s] = mpos[s] > 0 ? p.C[off] : 0.0;
+        if (mpos[s] > 0) {
+          Wn[r][s] = (double)pd[s] - pc[s] * Wn[r][s];
+          buf[lp(mpos[s])] = (T)Wn[r][s];
+        }
       }
-    }
-    T out[NS];
-    line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      if (tl == 0) buf[lp(0)] = (T)0;
+      line_sync<WPL>();
+      if (r + 1 < nr) {
+        fetch_d(l, r + 1);
+      } else if (l > 1) {
+        fetch_d(l - 1, 0);
+      }
+      if (r == 0 && l > 1) fetch_c(l - 1, pcn);
+      T out[NS];
+      line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (mpos[s] > 0) line_p[mpos[s]] = out[s];
-    line_sync<WPL>();
+      for (int s = 0; s < NS; ++s)
+        if (mpos[s] > 0) line_p[mpos[s]] = out[s];
+      line_sync<WPL>();
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pc[s] = pcn[s];
   }
 }
 
-template <typename T, int MY, int WPL = default_wpl<MY>()>
-__global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p) {
+template <typename T, int MY, int WPL, int NR>
+__global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
-  yback_block<T, MY, WPL>(p, blockIdx.x, blockIdx.y, smem, tab);
+  const int r0 = blockIdx.y * NR;
+  yback_block<T, MY, WPL, NR>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
