@@ -77,7 +77,7 @@ __device__ __forceinline__ void dispatch_m(int M, Fn&& fn) {
 // RHS pass
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
-  __shared__ double win[5][kSY * kSX];
+  __shared__ double win[kRSlots][kSY * kSX];
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev& p = b.P[b.perm[k]];

@@ -621,10 +621,10 @@ static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream
 static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, double* R,
                                 int nrhs, int slot, hipStream_t s) {
   const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
-  dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
+  dim3 grid((p->d.nx + kQTX - 1) / kQTX, (p->d.ny + kQTY - 1) / kQTY, nzc * nrhs);
   if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
   double* acc = slot >= 0 ? reinterpret_cast<double*>(p->dstats) + slot : nullptr;
-  hipLaunchKernelGGL(k_residual, grid, dim3(kRThreads), 0, s, pd, F, U, R, acc);
+  hipLaunchKernelGGL(k_residual, grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
   return hipGetLastError();
 }
 

@@ -143,11 +143,16 @@ __device__ __forceinline__ int linear_block() {
 }
 
 // ---------------------------------------------------------------------------
-// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 512 threads
-// (64 x 8, two y-rows each), marching over kZChunk planes with two planes in flight.
+// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 256 threads; thread
+// (lane, wave) owns column x0 + lane, rows y0 + 4 wave .. + 3.  The workgroup marches
+// over a z-chunk with a four-plane ring of halo tiles in LDS (the planes l-1, l, l+1
+// and the next one) and two further planes in flight in registers; every thread keeps
+// its own column of the five planes l-2 .. l+2 in registers, so the z-differences and
+// the y-differences inside its rows cost no LDS reads.
 // ---------------------------------------------------------------------------
 constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;  // kZChunk: default planes per workgroup
 constexpr int kSX = kRX + 2 * kRH, kSY = kRY + 2 * kRH;
+constexpr int kRSlots = 4;  // LDS planes
 
 __device__ __forceinline__ double d4_onesided(const double* c, long long s, bool low) {
   // fourth difference at the first (low) or last interior layer: one-sided 6-point
@@ -165,8 +170,8 @@ __device__ __forceinline__ double plane9(const double* __restrict__ w, const dou
          w[2] * (c[-sy] + c[sy]) + w[3] * c[0];
 }
 
-constexpr int kRThreads = 512;
-constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread
+constexpr int kRThreads = 256;
+constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread (4)
 constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
 // one 64 x 16 tile (bx, by) over the z-chunk zc of right-hand side r
@@ -178,10 +183,9 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
   const int le = min(p.nz, lb + p.zchunk - 1);
   const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
   const double* __restrict__ f = p.f + r * p.f_stride;
-  const int halo = (p.scheme == kHelm6) ? 2 : 1;
 
   // this thread's share of a plane tile: in-plane offsets, fixed for every plane
-  long long off[kRLoads];
+  int off[kRLoads];
   bool ok[kRLoads];
 #pragma unroll
   for (int k = 0; k < kRLoads; ++k) {
@@ -189,108 +193,184 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
     const int yy = e / kSX, xx = e - yy * kSX;
     const int gx = x0 - kRH + xx, gy = y0 - kRH + yy;
     ok[k] = e < kSY * kSX && gx >= 0 && gx <= p.nx + 1 && gy >= 0 && gy <= p.ny + 1;
-    off[k] = ok[k] ? gx + sy * gy : 0;
+    off[k] = ok[k] ? gx + (int)sy * gy : 0;
   }
-  // two planes in flight in registers
-  double pa[kRLoads], pb[kRLoads];
   auto fetch = [&](double(&pre)[kRLoads], int q) {
     const bool qok = q >= 0 && q <= p.nz + 1;
+    const double* fq = f + sz * (qok ? q : 0);
 #pragma unroll
-    for (int k = 0; k < kRLoads; ++k) pre[k] = (qok && ok[k]) ? f[off[k] + sz * q] : 0.0;
+    for (int k = 0; k < kRLoads; ++k) pre[k] = (qok && ok[k]) ? fq[off[k]] : 0.0;
   };
+  auto slot = [](int q) { return (q + 2 * kRSlots) % kRSlots; };
   auto stash = [&](const double(&pre)[kRLoads], int q) {
-    double* w = win[(q + 5) % 5];
+    double* w = win[slot(q)];
 #pragma unroll
     for (int k = 0; k < kRLoads; ++k) {
       const int e = threadIdx.x + kRThreads * k;
       if (e < kSY * kSX) w[e] = pre[k];
     }
   };
-  for (int q = lb - halo; q < lb + halo; ++q) {
+  // tile index of this thread's row k
+  const int cbase = (ty * kRRows + kRH) * kSX + tx + kRH;
+  // own column of planes l-2 .. l+2
+  double cz[5][kRRows];
+  auto own = [&](double(&dst)[kRRows], int q) {
+    const double* w = win[slot(q)];
+#pragma unroll
+    for (int k = 0; k < kRRows; ++k) dst[k] = w[cbase + k * kSX];
+  };
+
+  // prologue: planes lb-2 .. lb+1 into the ring and their own columns into registers,
+  // then plane lb+2 over lb-2's slot; two further planes in flight in pa, pb (the step
+  // of plane l stashes plane l+3 from the buffer (l - lb) mod 2 and refills that buffer
+  // with plane l+5)
+  double pa[kRLoads], pb[kRLoads];
+  for (int q = lb - 2; q <= lb + 1; ++q) {
     fetch(pa, q);
     stash(pa, q);
   }
-  fetch(pa, lb + halo);
-  fetch(pb, lb + halo + 1);
+  fetch(pa, lb + 2);
+  if (lb < le) fetch(pb, lb + 3);
+  __syncthreads();
+  own(cz[0], lb - 2);
+  own(cz[1], lb - 1);
+  own(cz[2], lb);
+  own(cz[3], lb + 1);
+  __syncthreads();
+  stash(pa, lb + 2);
+  if (lb + 1 < le) fetch(pa, lb + 4);
+  __syncthreads();
+  own(cz[4], lb + 2);
 
   const int i = x0 + tx;
-  const double hz2 = p.hz * p.hz;
+  const double hz2 = p.hz * p.hz, h = p.hz;
   auto compute = [&](int l) {
-    const double* P0 = win[(l + 5) % 5];
-    const double* Pm = win[(l + 4) % 5];
-    const double* Pp = win[(l + 6) % 5];
-    const double* Pmm = win[(l + 3) % 5];
-    const double* Ppp = win[(l + 7) % 5];
+    const double* P0 = win[slot(l)];
+    const double* Pm = win[slot(l - 1)];
+    const double* Pp = win[slot(l + 1)];
     const double kl = p.k2[l], kzl = p.k2z[l];
-#pragma unroll 1
+    // y-neighbours: own registers inside the thread's rows, LDS outside
+    auto y0v = [&](int k, int d) -> double {
+      const int kk = k + d;
+      return (kk >= 0 && kk < kRRows) ? cz[2][kk] : P0[cbase + kk * kSX];
+    };
+    auto ymv = [&](int k, int d) -> double {
+      const int kk = k + d;
+      return (kk >= 0 && kk < kRRows) ? cz[1][kk] : Pm[cbase + kk * kSX];
+    };
+    auto ypv = [&](int k, int d) -> double {
+      const int kk = k + d;
+      return (kk >= 0 && kk < kRRows) ? cz[3][kk] : Pp[cbase + kk * kSX];
+    };
+#pragma unroll
     for (int k = 0; k < kRRows; ++k) {
-      const int yl = ty * kRRows + k, j = y0 + yl;
+      const int j = y0 + ty * kRRows + k;
       if (i > p.nx || j > p.ny) continue;
-      const int c0 = (yl + kRH) * kSX + tx + kRH;  // tile index of (i, j)
-      const double f0 = P0[c0];
+      const int c0 = cbase + k * kSX;
+      const double f0 = cz[2][k];
       double F;
       if (p.scheme == kHelm2) {
         F = hz2 * f0;
       } else {
+        // A: the 6 face neighbours
         const double ax = P0[c0 - 1] + P0[c0 + 1];
-        const double ay = P0[c0 - kSX] + P0[c0 + kSX];
-        const double az = Pm[c0] + Pp[c0];
-        const double d2x = ax - 2.0 * f0, d2y = ay - 2.0 * f0, d2z = az - 2.0 * f0;
+        const double ay = y0v(k, -1) + y0v(k, 1);
+        const double az = cz[1][k] + cz[3][k];
+        const double A = ax + ay + az;
         if (p.scheme == kHelm4) {
-          F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
+          // f + h^2/12 sum d2  =  f/2 + A/12
+          F = hz2 * (0.5 * f0 + A * (1.0 / 12.0));
         } else if (p.scheme == kCd4) {
-          const double dz1 = 0.5 * (Pp[c0] - Pm[c0]);
-          F = hz2 * (f0 + (d2x + d2y) * (1.0 / 12.0) + (p.hz * p.gamma * dz1 + d2z) * (1.0 / 12.0));
+          // f + (d2x + d2y)/12 + (h gamma f_z + d2z)/12 with central f_z
+          F = hz2 * (0.5 * f0 + A * (1.0 / 12.0) + p.hz * p.gamma * (cz[3][k] - cz[1][k]) * (1.0 / 24.0));
         } else {
           // 6th order: f + h^2/12 sum d2 - h^4/240 sum d4 + h^4/90 sum d2d2 - h^2 k^2 f/20
-          //            + h^4 (k^2)_z f_z/60, differences undivided
-          const double* c = f + i + sy * j + sz * l;
-          const double d4x = (i >= 2 && i <= p.nx - 1)
-                                 ? P0[c0 - 2] - 4.0 * P0[c0 - 1] + 6.0 * f0 - 4.0 * P0[c0 + 1] + P0[c0 + 2]
-                                 : d4_onesided(c, 1, i == 1);
-          const double d4y = (j >= 2 && j <= p.ny - 1)
-                                 ? P0[c0 - 2 * kSX] - 4.0 * P0[c0 - kSX] + 6.0 * f0 - 4.0 * P0[c0 + kSX] +
-                                       P0[c0 + 2 * kSX]
-                                 : d4_onesided(c, sy, j == 1);
-          const double d4z = (l >= 2 && l <= p.nz - 1)
-                                 ? Pmm[c0] - 4.0 * Pm[c0] + 6.0 * f0 - 4.0 * Pp[c0] + Ppp[c0]
-                                 : d4_onesided(c, sz, l == 1);
+          // + h^4 (k^2)_z f_z/60, differences undivided, collected by stencil point:
+          //   (67/120 - h^2 k^2/20) f + A/18 + E/90 - E2/240 + h^3 (k^2)_z (f_{l+1} - f_{l-1})/120
+          // with E the 12 edge and E2 the 6 axis-distance-2 neighbours.  On the faces of
+          // the interior box the axis-distance-2 values outside the grid are zeros here;
+          // the one-sided fourth differences replace them below.
+          const double e2 = P0[c0 - 2] + P0[c0 + 2] + y0v(k, -2) + y0v(k, 2) + cz[0][k] + cz[4][k];
           const double exy = P0[c0 - kSX - 1] + P0[c0 - kSX + 1] + P0[c0 + kSX - 1] + P0[c0 + kSX + 1];
           const double exz = Pm[c0 - 1] + Pm[c0 + 1] + Pp[c0 - 1] + Pp[c0 + 1];
-          const double eyz = Pm[c0 - kSX] + Pm[c0 + kSX] + Pp[c0 - kSX] + Pp[c0 + kSX];
-          const double dxy = exy - 2.0 * (ax + ay) + 4.0 * f0;
-          const double dxz = exz - 2.0 * (ax + az) + 4.0 * f0;
-          const double dyz = eyz - 2.0 * (ay + az) + 4.0 * f0;
-          const double h = p.hz;
-          F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - (d4x + d4y + d4z) * (1.0 / 240.0) +
-                     (dxy + dxz + dyz) * (1.0 / 90.0) - h * h * kl * f0 * (1.0 / 20.0) +
-                     h * h * h * kzl * (Pp[c0] - Pm[c0]) * (1.0 / 120.0));
+          const double eyz = ymv(k, -1) + ymv(k, 1) + ypv(k, -1) + ypv(k, 1);
+          const double E = exy + exz + eyz;
+          F = hz2 * ((67.0 / 120.0 - h * h * kl * (1.0 / 20.0)) * f0 + A * (1.0 / 18.0) + E * (1.0 / 90.0) -
+                     e2 * (1.0 / 240.0) + h * h * h * kzl * (cz[3][k] - cz[1][k]) * (1.0 / 120.0));
         }
       }
-      if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
-      if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
       p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] = F;
     }
-  };
-  for (int l = lb; l <= le; l += 2) {
-    stash(pa, l + halo);
-    __syncthreads();
-    if (l + 2 <= le) fetch(pa, l + halo + 2);
-    compute(l);
-    __syncthreads();
-    if (l + 1 <= le) {
-      stash(pb, l + 1 + halo);
-      __syncthreads();
-      if (l + 3 <= le) fetch(pb, l + halo + 3);
-      compute(l + 1);
-      __syncthreads();
+    // Points on a face of the interior box: the one-sided fourth differences of the
+    // 6th-order operator in place of the zero-padded central ones, and the lift of the
+    // z-face data, added to what was stored (a rolled loop, so the rarely taken global
+    // reads cost no registers in the code above)
+    const bool h6 = p.scheme == kHelm6;
+    const bool zface = l == 1 || l == p.nz;
+    const bool lift = (l == 1 && p.glo) || (l == p.nz && p.ghi);
+    const int jb = y0 + ty * kRRows;
+    const bool yface = jb == 1 || (jb <= p.ny && p.ny <= jb + kRRows - 1);
+    if (i <= p.nx && ((h6 && (zface || yface || i == 1 || i == p.nx)) || lift)) {
+#pragma unroll 1
+      for (int k = 0; k < kRRows; ++k) {
+        const int j = jb + k;
+        if (j > p.ny) break;
+        const double* c = f + i + sy * j + sz * l;
+        double d4 = 0.0, F = 0.0;
+        if (h6) {
+          // central fourth difference as formed above (values beyond the grid are zero)
+          auto padded = [&](long long st, bool low, bool high) {
+            const double m2 = low ? 0.0 : c[-2 * st], p2 = high ? 0.0 : c[2 * st];
+            return m2 + p2 - 4.0 * (c[-st] + c[st]) + 6.0 * c[0];
+          };
+          if (i == 1 || i == p.nx) d4 += d4_onesided(c, 1, i == 1) - padded(1, i == 1, i == p.nx);
+          if (j == 1 || j == p.ny) d4 += d4_onesided(c, sy, j == 1) - padded(sy, j == 1, j == p.ny);
+          if (zface) d4 += d4_onesided(c, sz, l == 1) - padded(sz, l == 1, l == p.nz);
+          F = -hz2 * d4 * (1.0 / 240.0);
+        }
+        if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
+        if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
+        if (F != 0.0) p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] += F;
+      }
     }
+  };
+  // step l: compute plane l; then plane l+3 replaces l-1 in the ring, its buffer is
+  // refilled with plane l+5, and the own columns move up by one plane
+  for (int l = lb; l <= le; l += 2) {
+    compute(l);
+    if (l == le) break;
+    __syncthreads();
+    stash(pb, l + 3);
+    if (l + 2 < le) fetch(pb, l + 5);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRRows; ++k) {
+      cz[0][k] = cz[1][k];
+      cz[1][k] = cz[2][k];
+      cz[2][k] = cz[3][k];
+      cz[3][k] = cz[4][k];
+    }
+    own(cz[4], l + 3);
+    compute(l + 1);
+    if (l + 1 == le) break;
+    __syncthreads();
+    stash(pa, l + 4);
+    if (l + 3 < le) fetch(pa, l + 6);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRRows; ++k) {
+      cz[0][k] = cz[1][k];
+      cz[1][k] = cz[2][k];
+      cz[2][k] = cz[3][k];
+      cz[3][k] = cz[4][k];
+    }
+    own(cz[4], l + 4);
   }
 }
 
 // grid: (x tiles) x (y tiles) x (z chunks x right-hand sides), taken in XCD order
 __global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
-  __shared__ double win[5][kSY * kSX];
+  __shared__ double win[kRSlots][kSY * kSX];
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
@@ -694,18 +774,19 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 // interior points, 512 threads (two y-rows each), marching over kZChunk planes with a
 // three-plane window of U (halo 1) in LDS and two planes in flight in registers.
 // ---------------------------------------------------------------------------
-constexpr int kQX = 64 + 2, kQY = 16 + 2;
-constexpr int kQLoads = (kQX * kQY + kRThreads - 1) / kRThreads;
+constexpr int kQTX = 64, kQTY = 16, kQThreads = 512, kQRows = kQTY / (kQThreads / 64);
+constexpr int kQX = kQTX + 2, kQY = kQTY + 2;
+constexpr int kQLoads = (kQX * kQY + kQThreads - 1) / kQThreads;
 
-__global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double* __restrict__ Fi,
+__global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double* __restrict__ Fi,
                                                         const double* __restrict__ U, double* __restrict__ R,
                                                         double* acc) {
   __shared__ double win[3][kQX * kQY];
-  __shared__ double part[kRThreads / 64];
+  __shared__ double part[kQThreads / 64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
-  const int x0 = 1 + bx * kRX, y0 = 1 + by * kRY;
+  const int x0 = 1 + bx * kQTX, y0 = 1 + by * kQTY;
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int zc = bz % nzc, r = bz / nzc;
   const int lb = 1 + zc * p.zchunk;
@@ -716,7 +797,7 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
   bool ok[kQLoads];
 #pragma unroll
   for (int k = 0; k < kQLoads; ++k) {
-    const int e = threadIdx.x + kRThreads * k;
+    const int e = threadIdx.x + kQThreads * k;
     const int yy = e / kQX, xx = e - yy * kQX;
     const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;  // interior indices, 1-based
     ok[k] = e < kQX * kQY && gx >= 1 && gx <= p.nx && gy >= 1 && gy <= p.ny;
@@ -732,7 +813,7 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
     double* w = win[(q + 3) % 3];
 #pragma unroll
     for (int k = 0; k < kQLoads; ++k) {
-      const int e = threadIdx.x + kRThreads * k;
+      const int e = threadIdx.x + kQThreads * k;
       if (e < kQX * kQY) w[e] = pre[k];
     }
   };
@@ -750,8 +831,8 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
     const double* Pp = win[(l + 1) % 3];
     const double* Wl = p.W + (l - 1) * 12;
 #pragma unroll 1
-    for (int k = 0; k < kRRows; ++k) {
-      const int yl = ty * kRRows + k, j = y0 + yl;
+    for (int k = 0; k < kQRows; ++k) {
+      const int yl = ty * kQRows + k, j = y0 + yl;
       if (i > p.nx || j > p.ny) continue;
       const int c = (yl + 1) * kQX + tx + 1;
       double au = 0.0;
@@ -788,7 +869,7 @@ __global__ void __launch_bounds__(kRThreads) k_residual(ProbDev p, const double*
   __syncthreads();
   if (threadIdx.x == 0 && acc) {
     double t = 0.0;
-    for (int q = 0; q < kRThreads / 64; ++q) t += part[q];
+    for (int q = 0; q < kQThreads / 64; ++q) t += part[q];
     atomicAdd(acc, t);
   }
 }
