@@ -94,14 +94,14 @@ template <typename T, int MX>
 __device__ __forceinline__ void xfwd_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
   constexpr int NS = Tx<MX, 1>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
   T* buf = lines + w * bufn;
   const XTile x = decode_xtile(p, t, w);
   if (x.active) {
     const double* Fr = p.F + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
-    if (lane == 0) buf[lp(0)] = (T)0;
-    for (int i = 1 + lane; i <= p.nx; i += 64) buf[lp(i)] = (T)Fr[i - 1];
+    if (lane == 0) buf[0] = (T)0;
+    for (int i = 1 + lane; i <= p.nx; i += 64) buf[i] = (T)Fr[i - 1];
   }
   __syncthreads();
   T out[NS];
@@ -129,7 +129,7 @@ template <typename T, int MX>
 __device__ __forceinline__ void xinv_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
   constexpr int NS = Tx<MX, 1>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
   T* buf = lines + w * bufn;
   const XTile x = decode_xtile(p, t, w);

@@ -367,14 +367,14 @@ extern "C" cs3d_status cs3d_set_workspace(cs3d_plan p, void* dev, size_t bytes) 
 // ---------------------------------------------------------------------------
 template <typename T, int MX>
 static size_t lds_bytes_x_t(const cs3d_plan p) {
-  const size_t a = (size_t)kTileJ * line_buf_elems<T, MX>(p->d.nx) * sizeof(T);
+  const size_t a = (size_t)kTileJ * line_buf_elems<T, MX, 1>(p->d.nx) * sizeof(T);
   const size_t b = (size_t)kTileJ * tile_stride(p->d.nx) * sizeof(T);
   return (a > b ? a : b) + tw_bytes<T, MX>();
 }
 
 template <typename T, int MY, int WPL = default_wpl<MY>()>
 static size_t lds_bytes_y_t(const cs3d_plan p) {
-  return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
+  return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY, WPL>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
 }
 
 template <typename KernelT, typename... Args>
@@ -919,15 +919,34 @@ static double line_cost(int f, int N) { return f ? f * std::log2((double)f) : 0.
 
 static int y_wpl(int fy) { return fy == 1024 ? 2 : 1; }
 
-// LDS elements (doubles) of one line buffer, as line_buf_elems for T = double
-static size_t line_elems(int f, int N) { return (size_t)(f ? lp(f) : lp(((N + 1 + 63) / 64) * 64)); }
+// LDS elements (doubles) of one line buffer, as line_buf_elems for T = double with the
+// default waves per line
+static size_t line_elems(int f, int N) {
+  switch (f) {
+    case 64: return line_buf_elems<double, 64, 1>(N);
+    case 128: return line_buf_elems<double, 128, 1>(N);
+    case 256: return line_buf_elems<double, 256, 1>(N);
+    case 512: return line_buf_elems<double, 512, default_wpl<512>()>(N);
+    case 1024: return line_buf_elems<double, 1024, default_wpl<1024>()>(N);
+    default: return line_buf_elems<double, 0, 1>(N);
+  }
+}
+
+// as above for the x passes (one wave per line)
+static size_t line_elems_x(int f, int N) {
+  switch (f) {
+    case 512: return line_buf_elems<double, 512, 1>(N);
+    case 1024: return line_buf_elems<double, 1024, 1>(N);
+    default: return line_elems(f, N);
+  }
+}
 
 template <int MAXM, bool DENSE>
 static cs3d_status batch_grids_t(cs3d_batch b) {
   size_t lx = 0, ly = 0;
   for (cs3d_plan q : b->plans) {
     const size_t ts = (size_t)tile_stride(q->d.nx);
-    const size_t bx = line_elems(q->fx, q->d.nx);
+    const size_t bx = line_elems_x(q->fx, q->d.nx);
     lx = std::max(lx, (size_t)kTileJ * std::max(bx, ts) * 8);
     ly = std::max(ly, (size_t)(kBlockY / (64 * y_wpl(q->fy))) * line_elems(q->fy, q->d.ny) * 8);
   }

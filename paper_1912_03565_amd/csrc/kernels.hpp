@@ -100,9 +100,9 @@ __device__ __forceinline__ int line_mode(int tl, int s, int N) {
 }
 
 // elements of T in one line buffer
-template <typename T, int M>
+template <typename T, int M, int WPL>
 __host__ __device__ constexpr int line_buf_elems(int N) {
-  return M ? fft_buf_elems<T, M>() : lp(((N + 1 + 63) / 64) * 64);
+  return M ? fft_buf_elems<T, M, WPL>() : ((N + 1 + 63) / 64) * 64;
 }
 
 // twiddle table bytes (FFT path only)
@@ -111,8 +111,10 @@ __host__ __device__ constexpr int tw_bytes() {
   return M ? tw_entries<M>() * (int)sizeof(cx<T>) : 0;
 }
 
-// odd row stride (>= nx + 1) of the K1/K4 transpose tile
-__host__ __device__ constexpr int tile_stride(int nx) { return (nx & 1) ? nx + 2 : nx + 1; }
+// row stride (>= nx + 1, = 4 mod 32) of the K1/K4 transpose tile: the transposed
+// accesses (8 rows x 4 columns per half-wave) then hit 32 distinct bank pairs, and a
+// row starts 16-byte aligned
+__host__ __device__ constexpr int tile_stride(int nx) { return ((nx + 1 - 4 + 31) / 32) * 32 + 4; }
 
 // ---------------------------------------------------------------------------
 // Hide a value from loop-invariant code motion (an empty asm statement that claims to
@@ -409,9 +411,9 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 1>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * bufn);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
   double pre[kNV];
@@ -428,11 +430,11 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
     __syncthreads();  // the previous tile's store phase is done with the LDS
-    if (lane == 0) buf[lp(0)] = (T)0;
+    if (lane == 0) buf[0] = (T)0;
 #pragma unroll
     for (int k = 0; k < kNV; ++k) {
       const int i = 1 + lane + 64 * k;
-      if (i <= p.nx) buf[lp(i)] = (T)pre[k];
+      if (i <= p.nx) buf[i] = (T)pre[k];
     }
     if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
     __syncthreads();  // also publishes the twiddle table on the first pass
@@ -503,7 +505,7 @@ struct YCfg {
 // twiddle tables of a y pass, loaded by the whole block (a barrier follows)
 template <typename T, int MY, int WPL>
 __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load) {
-  const int bufn = line_buf_elems<T, MY>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
   cx<T>* tab = reinterpret_cast<cx<T>*>(smem + YCfg<MY, WPL>::LPB * bufn);
   if constexpr (MY != 0) {
     if (load) load_twiddles<T, MY, WPL>(tab, p.twy);
@@ -522,7 +524,7 @@ template <typename T, int MY, int WPL, int NR>
 __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL>;
   constexpr int NS = C::NS;
-  const int bufn = line_buf_elems<T, MY>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
   const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
@@ -560,7 +562,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
 #pragma unroll
       for (int s = 0; s < C::NLD; ++s) {
         const int e = tl + C::LANES * s;
-        if (e <= p.ny) buf[lp(e)] = pre[s];
+        if (e <= p.ny) buf[e] = pre[s];
       }
       line_sync<WPL>();
       if (r + 1 < nr) fetch(l, r + 1);
@@ -625,7 +627,7 @@ template <typename T, int MY, int WPL, int NR>
 __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL>;
   constexpr int NS = C::NS;
-  const int bufn = line_buf_elems<T, MY>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
   const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
@@ -665,13 +667,26 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
       if (r >= nr) break;
       T* line_p = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        if (mpos[s] > 0) {
-          Wn[r][s] = (double)pd[s] - pc[s] * Wn[r][s];
-          buf[lp(mpos[s])] = (T)Wn[r][s];
+      for (int s = 0; s < NS; ++s)
+        if (mpos[s] > 0) Wn[r][s] = (double)pd[s] - pc[s] * Wn[r][s];
+      if constexpr (MY != 0) {
+        // modes 2q and 2q+1 of a lane are adjacent: one 16-byte store per pair (the
+        // slot of mode 0 is written but never read)
+        if (tl < FftGeom<MY, WPL>::L) {
+#pragma unroll
+          for (int s = 0; s < NS; s += 2) {
+            using V2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+            V2 w2;
+            w2.x = (T)Wn[r][s];
+            w2.y = (T)Wn[r][s + 1];
+            *reinterpret_cast<V2*>(buf + 2 * (tl + FftGeom<MY, WPL>::L * (s >> 1))) = w2;
+          }
         }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (mpos[s] > 0) buf[mpos[s]] = (T)Wn[r][s];
       }
-      if (tl == 0) buf[lp(0)] = (T)0;
       line_sync<WPL>();
       if (r + 1 < nr) {
         fetch_d(l, r + 1);
@@ -718,9 +733,9 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   constexpr int NS = Tx<MX, 1>::NS;
   constexpr int NT = (1023 * kTileJ + 64 * kTileJ - 1) / (64 * kTileJ);  // segment values per thread
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int bufn = line_buf_elems<T, MX>(p.nx);
+  const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * bufn);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
   T pre[NT];

@@ -14,11 +14,15 @@
 // lane e mod L, slot e div L, on input and on output, so butterflies run in
 // registers and only the transposes between stages go through LDS.
 //
-// LDS layout: every line buffer is indexed through lp(p) = p + p/16, one pad
-// element per 16, so the stride-16 writes of the Stockham stages and the
-// stride-2 accesses of the DST slots fall in distinct banks.  A buffer holds
-// lp(M) elements; FP64 exchanges move the real and then the imaginary parts
-// through it, FP32 exchanges move complex pairs in one go.
+// LDS layout.  The LDS of gfx950 serves 64 banks of 4 bytes; an 8-byte access of a
+// wavefront is conflict-free when, within each half-wave, the 8-byte slot indices are
+// distinct modulo 32 (measured: contiguous runs and odd strides are free, a stride of
+// 2^k slots costs 2^k-fold).  The line input is stored unpadded (contiguous and
+// mirrored reads are then free); every Stockham exchange uses its own index map of the
+// buffer (pad one slot per 2^a, or an XOR of the low five bits with higher ones),
+// chosen per transform size so that the stage's writes and the next stage's reads are
+// conflict-free or nearly so.  FP64 exchanges move the real and then the imaginary
+// parts through the buffer, FP32 exchanges move complex pairs in one go.
 //
 // Twiddles live in LDS, filled once per workgroup: tab[n] = exp(-i pi n/M), n < M, for
 // the pre-processing, and after it one table per Stockham stage (radix RS, span NSP)
@@ -50,7 +54,26 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 template <typename T>
 __device__ __forceinline__ cx<T> cmi(cx<T> a) { return {a.im, -a.re}; }
 
-__host__ __device__ constexpr int lp(int p) { return p + (p >> 4); }
+// index maps of a line buffer: identity, one pad slot per 2^a (a = 3, 4, 5), XOR of the
+// low five bits with bits 4..8 (a bijection inside each aligned block of 32)
+constexpr int kLayId = 0, kLayPad3 = 3, kLayPad4 = 4, kLayPad5 = 5, kLayXor4 = 14;
+
+template <int LAY>
+__host__ __device__ constexpr int lay(int p) {
+  if constexpr (LAY == kLayId) {
+    return p;
+  } else if constexpr (LAY == kLayXor4) {
+    return p ^ ((p >> 4) & 31);
+  } else {
+    return p + (p >> LAY);
+  }
+}
+
+// slots a map needs for M elements
+template <int LAY>
+__host__ __device__ constexpr int lay_slots(int M) {
+  return (LAY == kLayId || LAY == kLayXor4) ? M : M + (M >> LAY);
+}
 
 // Compiler-level ordering point for LDS traffic inside one wavefront.  LDS
 // instructions of a wave execute in program order, so a wave-private buffer
@@ -174,10 +197,29 @@ using LineRegs = cx<T>[FftGeom<M, WPL>::R];
 template <typename T, int M, int WPL>
 using LineOut = T[FftGeom<M, WPL>::R];
 
+// index map of exchange k of the stage plan of (M, WPL) (see fft_run)
+template <int M, int WPL, int K>
+__host__ __device__ constexpr int exch_lay() {
+  if constexpr (M == 64) return K == 0 ? kLayPad4 : kLayPad3;
+  else if constexpr (M == 128 || M == 256) return K == 0 ? kLayPad5 : (K == 1 ? kLayXor4 : kLayId);
+  else if constexpr (M == 512 && WPL == 1) return K == 0 ? kLayPad5 : kLayPad3;
+  else if constexpr (M == 512) return K == 0 ? kLayPad5 : (K == 1 ? kLayXor4 : kLayId);
+  else if constexpr (WPL == 1) return K == 0 ? kLayPad5 : kLayXor4;
+  else return K == 0 ? kLayPad5 : (K == 1 ? kLayPad3 : kLayId);
+}
+
+template <int M, int WPL>
+__host__ __device__ constexpr int fft_slots() {
+  constexpr int a = lay_slots<exch_lay<M, WPL, 0>()>(M), b = lay_slots<exch_lay<M, WPL, 1>()>(M),
+                c = lay_slots<exch_lay<M, WPL, 2>()>(M), d = lay_slots<exch_lay<M, WPL, 3>()>(M);
+  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
 // LDS elements of T in one line buffer
-template <typename T, int M>
+template <typename T, int M, int WPL>
 __host__ __device__ constexpr int fft_buf_elems() {
-  return sizeof(T) == 8 ? lp(M) : 2 * lp(M);
+  return sizeof(T) == 8 ? fft_slots<M, WPL>() : 2 * fft_slots<M, WPL>();
 }
 
 // LDS complex entries of the twiddle tables of one FFT size
@@ -234,44 +276,46 @@ __device__ __forceinline__ void fft_stage(LineRegs<T, M, WPL>& v, int tl, const 
 
 // LDS positions of the transpose between stage (RS, NSP) and a following stage of
 // radix RS2 (recomputed where used, so they do not occupy registers)
-template <int M, int WPL, int RS, int NSP>
+template <int M, int WPL, int RS, int NSP, int LAY>
 __device__ __forceinline__ int fft_opos(int tl, int s) {
   constexpr int L = FftGeom<M, WPL>::L, NB = FftGeom<M, WPL>::R / RS;
   const int b = s % NB, r = s / NB;
   const int j = tl + L * b;
-  return lp((j / NSP) * NSP * RS + (j & (NSP - 1)) + r * NSP);
+  return lay<LAY>((j / NSP) * NSP * RS + (j & (NSP - 1)) + r * NSP);
 }
 
-template <int M, int WPL, int RS2>
+template <int M, int WPL, int RS2, int LAY>
 __device__ __forceinline__ int fft_ipos(int tl, int s) {
   constexpr int L = FftGeom<M, WPL>::L, NB2 = FftGeom<M, WPL>::R / RS2;
   const int b = s % NB2, r = s / NB2;
-  return lp(tl + L * b + r * (M / RS2));
+  return lay<LAY>(tl + L * b + r * (M / RS2));
 }
 
-template <typename T, int M, int WPL, int RS, int NSP, int RS2>
+// exchange K of the plan: after stage (RS, NSP), before a stage of radix RS2
+template <typename T, int M, int WPL, int RS, int NSP, int RS2, int K>
 __device__ __forceinline__ void fft_exchange(LineRegs<T, M, WPL>& v, T* buf, int tl) {
   constexpr int R = FftGeom<M, WPL>::R;
+  constexpr int LAY = exch_lay<M, WPL, K>();
   if constexpr (sizeof(T) == 4) {
     cx<T>* cb = reinterpret_cast<cx<T>*>(buf);
 #pragma unroll
-    for (int s = 0; s < R; ++s) cb[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s];
+    for (int s = 0; s < R; ++s) cb[fft_opos<M, WPL, RS, NSP, LAY>(tl, s)] = v[s];
     line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s] = cb[fft_ipos<M, WPL, RS2>(tl, s)];
+    for (int s = 0; s < R; ++s) v[s] = cb[fft_ipos<M, WPL, RS2, LAY>(tl, s)];
     line_sync<WPL>();
   } else {
 #pragma unroll
-    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s].re;
+    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP, LAY>(tl, s)] = v[s].re;
     line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s].re = buf[fft_ipos<M, WPL, RS2>(tl, s)];
+    for (int s = 0; s < R; ++s) v[s].re = buf[fft_ipos<M, WPL, RS2, LAY>(tl, s)];
     line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP>(tl, s)] = v[s].im;
+    for (int s = 0; s < R; ++s) buf[fft_opos<M, WPL, RS, NSP, LAY>(tl, s)] = v[s].im;
     line_sync<WPL>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s].im = buf[fft_ipos<M, WPL, RS2>(tl, s)];
+    for (int s = 0; s < R; ++s) v[s].im = buf[fft_ipos<M, WPL, RS2, LAY>(tl, s)];
     line_sync<WPL>();
   }
 }
@@ -316,63 +360,63 @@ __device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, 
   constexpr int R = FftGeom<M, WPL>::R;
   if constexpr (R == 4 && M == 64) {
     fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 1, 4, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 4, 4, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
   } else if constexpr (R == 4 && M == 128) {
     fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 1, 4, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 4, 4, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 16, 2>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 16, 2, 2>(v, buf, tl);
     fft_stage<T, M, WPL, 2, 64, 60>(v, tl, st);
   } else if constexpr (R == 4 && M == 256) {
     fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 1, 4, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 4, 4, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 16, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 16, 4, 2>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 64, 60>(v, tl, st);
   } else if constexpr (R == 4 && M == 512) {
     fft_stage<T, M, WPL, 4, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 1, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 1, 4, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 4, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 4, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 4, 4, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 16, 12>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 16, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 16, 4, 2>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 64, 60>(v, tl, st);
-    fft_exchange<T, M, WPL, 4, 64, 2>(v, buf, tl);
+    fft_exchange<T, M, WPL, 4, 64, 2, 3>(v, buf, tl);
     fft_stage<T, M, WPL, 2, 256, 252>(v, tl, st);
   } else if constexpr (R == 8 && M == 512) {
     fft_stage<T, M, WPL, 8, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 1, 8>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 1, 8, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 8, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 8, 8>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 8, 8, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
   } else if constexpr (R == 8 && M == 1024) {
     fft_stage<T, M, WPL, 8, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 1, 8>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 1, 8, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 8, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 8, 8>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 8, 8, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 64, 2>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 64, 2, 2>(v, buf, tl);
     fft_stage<T, M, WPL, 2, 512, 504>(v, tl, st);
   } else {
     static_assert(R == 16 && M == 1024, "no stage plan");
     fft_stage<T, M, WPL, 16, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 16, 1, 16>(v, buf, tl);
+    fft_exchange<T, M, WPL, 16, 1, 16, 0>(v, buf, tl);
     fft_stage<T, M, WPL, 16, 16, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 16, 16, 4>(v, buf, tl);
+    fft_exchange<T, M, WPL, 16, 16, 4, 1>(v, buf, tl);
     fft_stage<T, M, WPL, 4, 256, 240>(v, tl, st);
   }
 }
 
-// DST-I of a line.  The input x_n (1 <= n < M) is read from src[n] (unpadded; src
-// may alias nothing the exchanges write before the first sync) or, when src is
-// null, from buf[lp(n)].  BLOCK_SYNC makes the sync after the input has been read a
+// DST-I of a line.  The input x_n (1 <= n < M) is read from src[n] (src may alias
+// nothing the exchanges write before the first sync) or, when src is null, from
+// buf[n] (unpadded).  BLOCK_SYNC makes the sync after the input has been read a
 // workgroup barrier, for callers whose line buffers overlay a shared input tile.
 // tl is the lane index within the line (0 <= tl < 64 WPL).  On return, lane tl < L
 // holds out[s] = S_m for m = fft_mode<M, WPL>(tl, s); buf is clobbered.  All lanes
@@ -389,8 +433,8 @@ __device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl,
       if (n == 0) {
         v[s] = {(T)0, (T)0};
       } else {
-        const T a = src ? src[n] : buf[lp(n)];
-        const T b = src ? src[M - n] : buf[lp(M - n)];
+        const T a = src ? src[n] : buf[n];
+        const T b = src ? src[M - n] : buf[M - n];
         const T u = a - b, z = a + b;
         const cx<T> t = tab[n];  // (cos, -sin)(pi n/M)
         v[s] = {u - z * t.im, z * t.re};
@@ -422,7 +466,7 @@ __device__ __forceinline__ int fft_mode(int tl, int s) {
 
 // ---------------------------------------------------------------------------
 // Dense path: any N <= 1024, one wave per line.  out[s] = S_k, k = 1 + lane + 64 s.
-// sintab[r] = sin(pi r/M), r < 2M.  The line is read from buf[lp(n)].
+// sintab[r] = sin(pi r/M), r < 2M.  The line is read from buf[n].
 // ---------------------------------------------------------------------------
 constexpr int kDenseSlots = 16;
 
@@ -439,7 +483,7 @@ __device__ __forceinline__ void dst_dense(const T* buf, int N, T (&out)[kDenseSl
       for (int n = 1; n <= N; ++n) {
         idx += k;
         if (idx >= twoM) idx -= twoM;
-        acc += (src ? src[n] : buf[lp(n)]) * (T)sintab[idx];
+        acc += (src ? src[n] : buf[n]) * (T)sintab[idx];
       }
     }
     out[s] = acc;
