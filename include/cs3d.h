@@ -162,7 +162,8 @@ cs3d_status cs3d_reset_timers(cs3d_plan plan);
  * changes the rounding of the transform only. */
 typedef struct {
   int zchunk;    /* z-planes per workgroup of the z-marching passes (RHS operator and, on the
-                    mixed path, the FP64 residual): 8..512, default 32 */
+                    mixed path, the FP64 residual): 8..512, default 32, for nz >= 512
+                    64 (FP64) or 128 (mixed) */
   int xpersist;  /* x passes of a plan: 1 = a resident set of workgroups walks all tiles
                     (default), 0 = one workgroup per tile */
   int ywpl;      /* y passes of a plan where N_y+1 is 512 or 1024: waves per line, 1 or 2
@@ -171,7 +172,8 @@ typedef struct {
                     pass, so the longest items start first (default); 0 = order given */
   int graph;     /* batches: 1 = the passes of a solve are captured once into a HIP graph and
                     replayed (default); 0 = launched one by one, with per-pass timing */
-  int yrhs;      /* y passes of a plan: right-hand sides per workgroup, 1, 2 or 4 (default 1).
+  int yrhs;      /* y passes of a plan: right-hand sides per workgroup, 1, 2 or 4 (default 1
+                    for FP64, 2 for mixed precision).
                     Their tridiagonal systems share the modal eigenvalues, the pivots and
                     each read of c'; transform sizes whose lanes hold 16 modes use 1. */
 } cs3d_tuning;

@@ -273,6 +273,11 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   p->fy = fft_len(desc->ny);
   p->ldy = ((desc->ny + 1 + 15) / 16) * 16;
   p->tune.ywpl = (p->fy == 1024) ? 2 : 1;
+  // long z-columns: fewer halo planes per workgroup; FP32 transforms leave registers for
+  // two right-hand sides per y-pass workgroup (the autotuner's choices at 1023^3)
+  const bool mixed = desc->precision != CS3D_FP64;
+  p->tune.zchunk = desc->nz >= 512 ? (mixed ? 128 : 64) : kZChunk;
+  p->tune.yrhs = mixed ? 2 : 1;
   st = build_weights(*desc, p->hW);
   if (st != CS3D_OK) {
     plan_free(p);
