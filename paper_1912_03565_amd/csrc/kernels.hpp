@@ -721,9 +721,9 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
 // while the current tile is transformed.
 // ---------------------------------------------------------------------------
 #ifndef CS3D_INV_PREFETCH
-#define CS3D_INV_PREFETCH 0
+#define CS3D_INV_PREFETCH 1
 #endif
-// K4 register prefetch of the next tile (off by default: it costs spills at M = 1024)
+// K4 register prefetch of the next tile (on: the loads of the next tile fly during the transform)
 constexpr bool kInvPrefetch = CS3D_INV_PREFETCH != 0;
 
 template <typename T, int MX>
