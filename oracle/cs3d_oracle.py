@@ -36,10 +36,24 @@ listed with its justification in the design notes of the repository):
   R14 the convection-diffusion d_{l+-1} has an unbalanced parenthesis; read as
       2/3 - (R_zx+R_zy)/6 +- (h_z gamma/12)(4 - R_zx - R_zy +- h_z gamma).
   R15 "LU decomposition" of each tridiagonal = Thomas without pivoting.
+  R16 k may be complex (Section 1 allows it): the weights, the modal eigenvalues, the
+      right-hand side and U are then complex; the sine transforms are real and act on
+      the real and imaginary parts alike, so only the tridiagonal solves are complex.
 """
 import numpy as np
 
 SCHEMES = ("helm2", "helm4", "helm6", "cd4")
+
+
+def _num(x):
+    """x as a float64 array, or complex128 when x holds complex values (complex k)."""
+    a = np.asarray(x)
+    return a.astype(np.complex128 if np.iscomplexobj(a) else np.float64)
+
+
+def _complex_of(dtype):
+    """The complex type of a real working precision."""
+    return np.clongdouble if dtype == np.longdouble else np.complex128
 
 __all__ = [
     "SCHEMES", "stencil_weights", "rhs", "lift", "sine_matrix", "dst2",
@@ -57,12 +71,13 @@ def stencil_weights(scheme, nz, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamm
 
     k2, k2_z, k2_zz are samples of k^2, (k^2)_z, (k^2)_zz at the planes z_0..z_{nz+1}.
     """
-    W = np.zeros((nz, 3, 4))
+    cplx = any(v is not None and np.iscomplexobj(np.asarray(v)) for v in (k2, k2_z, k2_zz))
+    W = np.zeros((nz, 3, 4), dtype=np.complex128 if cplx else np.float64)
     rzx = hz * hz / (hx * hx)
     rzy = hz * hz / (hy * hy)
     ls = np.arange(1, nz + 1)
     if scheme in ("helm2", "helm4", "helm6"):
-        k2 = np.asarray(k2, dtype=np.float64)
+        k2 = _num(k2)
         km, k0, kp = k2[ls - 1], k2[ls], k2[ls + 1]
     if scheme == "helm2":
         # Section 3.2: five non-zero weights.
@@ -86,8 +101,8 @@ def stencil_weights(scheme, nz, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamm
         if not (np.isclose(hx, hz, rtol=1e-13, atol=0) and np.isclose(hy, hz, rtol=1e-13, atol=0)):
             raise ValueError("6th-order scheme needs hx == hy == hz")
         h = hz
-        kz = np.asarray(k2_z, dtype=np.float64)[ls]
-        kzz = np.asarray(k2_zz, dtype=np.float64)[ls]
+        kz = _num(k2_z)[ls]
+        kzz = _num(k2_zz)[ls]
         for o, s, kk in ((0, -1.0, km), (2, 1.0, kp)):
             W[:, o, 0] = 1.0 / 30.0
             bc = 1.0 / 10.0 + h ** 2 * kk / 90.0 + s * h ** 3 * kz / 120.0
@@ -146,7 +161,7 @@ def _d4(f, axis):
     """
     g = np.moveaxis(f, axis, 0)
     n = g.shape[0] - 2
-    out = np.empty((n,) + g.shape[1:])
+    out = np.empty((n,) + g.shape[1:], dtype=g.dtype)
     if n < 4:
         raise ValueError("the fourth differences need at least 4 interior points per axis")
     out[1:n - 1] = g[0:n - 2] - 4 * g[1:n - 1] + 6 * g[2:n] - 4 * g[3:n + 1] + g[4:n + 2]
@@ -183,7 +198,7 @@ def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0):
            where sum_alpha h^2 delta^2 f is corrected by -1/240 h^4 delta^4 so that the h^4
            coefficient of f_{alpha alpha alpha alpha} is 1/360.
     """
-    f = np.asarray(f, dtype=np.float64)
+    f = _num(f)
     nz = f.shape[0] - 2
     inner = f[1:-1, 1:-1, 1:-1]
     if scheme == "helm2":
@@ -195,8 +210,8 @@ def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0):
                           + (hz * gamma * _d1(f, 0) + _d2(f, 0)) / 12.0)
     if scheme == "helm6":
         h = hz
-        k0 = np.asarray(k2, dtype=np.float64)[1:nz + 1][:, None, None]
-        kz = np.asarray(k2_z, dtype=np.float64)[1:nz + 1][:, None, None]
+        k0 = _num(k2)[1:nz + 1][:, None, None]
+        kz = _num(k2_z)[1:nz + 1][:, None, None]
         s2 = _d2(f, 0) + _d2(f, 1) + _d2(f, 2)
         s4 = _d4(f, 0) + _d4(f, 1) + _d4(f, 2)
         sx = _d2d2(f, 1, 2) + _d2d2(f, 0, 2) + _d2d2(f, 0, 1)
@@ -219,11 +234,12 @@ def _plane9(w, P):
 
 def lift(W, F, g_lo=None, g_hi=None):
     """F_1 -= (plane -1 weights of row 1) * g_lo;  F_Nz -= (plane +1 weights of row Nz) * g_hi."""
-    F = np.array(F, dtype=np.float64, copy=True)
+    parts = [F, W] + [g for g in (g_lo, g_hi) if g is not None]
+    F = np.array(F, dtype=np.result_type(*[_num(x) for x in parts]), copy=True)
     if g_lo is not None:
-        F[0] -= _plane9(W[0, 0], np.asarray(g_lo, dtype=np.float64))
+        F[0] -= _plane9(W[0, 0], _num(g_lo))
     if g_hi is not None:
-        F[-1] -= _plane9(W[-1, 2], np.asarray(g_hi, dtype=np.float64))
+        F[-1] -= _plane9(W[-1, 2], _num(g_hi))
     return F
 
 
@@ -234,8 +250,8 @@ def apply_operator(W, U_closed):
     This is the residual path: it shares nothing with the transform solve.
     """
     U = np.asarray(U_closed)
-    if U.dtype != np.longdouble:
-        U = U.astype(np.float64)
+    if U.dtype not in (np.longdouble, np.clongdouble):
+        U = _num(U)
     nz = U.shape[0] - 2
     out = np.zeros((nz, U.shape[1] - 2, U.shape[2] - 2), dtype=np.result_type(U, W))
     for l in range(1, nz + 1):
@@ -264,6 +280,9 @@ def sine_matrix(n, dtype=np.float64):
 
 def dst2(F, dtype=None):
     """Fbar_l = V^T F_l for every plane: sums over x then over y (dense products)."""
+    if np.iscomplexobj(F):  # the transform is real: real and imaginary parts alike
+        re = dst2(np.real(F), dtype)
+        return re + 1j * dst2(np.imag(F), dtype)
     dtype = F.dtype if dtype is None else dtype
     F = np.asarray(F, dtype=dtype)
     nz, ny, nx = F.shape
@@ -280,7 +299,7 @@ def modal_eigenvalues(W, nx, ny, dtype=np.float64):
     pi = _pi(dtype)
     ct = np.cos(pi * np.arange(1, nx + 1, dtype=dtype) / (nx + 1))[None, :]
     cp = np.cos(pi * np.arange(1, ny + 1, dtype=dtype) / (ny + 1))[:, None]
-    W = np.asarray(W, dtype=dtype)
+    W = np.asarray(W, dtype=_complex_of(dtype) if np.iscomplexobj(W) else dtype)
     a, b, c, d = (W[..., q][:, :, None, None] for q in range(4))
     return 4.0 * a * cp * ct + 2.0 * b * ct + 2.0 * c * cp + d
 
@@ -318,7 +337,11 @@ def thomas(lam, Fbar):
 
 def solve_modal(W, Fbar):
     nz, ny, nx = Fbar.shape
-    return thomas(modal_eigenvalues(W, nx, ny, Fbar.dtype), Fbar)
+    real = np.real(Fbar[:1, :1, :1]).dtype
+    lam = modal_eigenvalues(W, nx, ny, real)
+    if np.iscomplexobj(lam) and not np.iscomplexobj(Fbar):
+        Fbar = Fbar.astype(_complex_of(real))
+    return thomas(lam, Fbar)
 
 
 class OracleResult:
@@ -345,7 +368,8 @@ def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
     Fl = lift(W, F, g_lo, g_hi)
     Fbar = dst2(Fl, dtype)
     What, minpiv, bad = solve_modal(W, Fbar)
-    U = dst2(What).astype(np.float64)    # V is its own inverse
+    U = dst2(What)    # V is its own inverse
+    U = U.astype(np.complex128 if np.iscomplexobj(U) else np.float64)
     return OracleResult(U, W, F, minpiv, bad)
 
 
@@ -355,7 +379,7 @@ def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
 # ----------------------------------------------------------------------------
 def assemble_dense(W, nx, ny, nz):
     n = nx * ny * nz
-    A = np.zeros((n, n))
+    A = np.zeros((n, n), dtype=np.result_type(W, np.float64))
     for l in range(nz):
         for j in range(ny):
             for i in range(nx):

@@ -429,3 +429,60 @@ def test_extended_precision_solve_has_tiny_residual(scheme, dims):
                  dtype=np.longdouble)
     ref = O.dense_solve(rq.W, O.lift(rq.W, rq.F, ql, qh))
     assert np.abs(rq.U - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Complex k(z) (absorbing media; reading R16)
+# ---------------------------------------------------------------------------
+def _csolve(p, dtype=np.float64, k2=None, f=None, g=True):
+    gl = p.g_lo[0].numpy() if (g and p.g_lo is not None) else None
+    gh = p.g_hi[0].numpy() if (g and p.g_hi is not None) else None
+    k2 = p.k2 if k2 is None else k2
+    return O.solve(p.scheme, p.f[0].numpy() if f is None else f, p.hx, p.hy, p.hz, k2, p.k2_z, p.k2_zz,
+                   p.gamma, gl, gh, dtype=dtype), gl, gh
+
+
+@pytest.mark.parametrize("scheme,n", [("helm2", (6, 5, 7)), ("helm4", (7, 4, 6)), ("helm6", (5, 6, 7)),
+                                      ("helm4", (3, 2, 1))])
+def test_complex_k_matches_dense_lu(scheme, n):
+    p = WL.complex_noise_problem(*n, scheme, seed=31 + sum(n))
+    assert np.iscomplexobj(p.k2)
+    res, gl, gh = _csolve(p)
+    ref = O.dense_solve(res.W, O.lift(res.W, res.F, gl, gh))
+    assert np.iscomplexobj(res.U) and np.abs(ref.imag).max() > 1e-3
+    assert np.abs(res.U - ref).max() <= 1e-12 * np.abs(ref).max()
+    # extended-precision transforms and Thomas on the same complex system
+    rl, _, _ = _csolve(p, dtype=np.longdouble)
+    assert np.abs(rl.U - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_complex_k_conjugate_medium_gives_conjugate_solution():
+    p = WL.complex_noise_problem(9, 8, 7, "helm6", seed=5, boundary=False)
+    f = p.f[0].numpy().real.copy()
+    r1, _, _ = _csolve(p, f=f)
+    r2 = O.solve("helm6", f, p.hx, p.hy, p.hz, np.conj(p.k2), np.conj(p.k2_z), np.conj(p.k2_zz))
+    assert np.abs(r2.U - np.conj(r1.U)).max() <= 1e-13 * np.abs(r1.U).max()
+    assert np.abs(r1.U.imag).max() > 1e-3 * np.abs(r1.U).max()
+
+
+def test_complex_data_with_real_k_splits_into_real_solves():
+    p = WL.noise_problem(9, 7, 8, "helm4", seed=6)
+    f = p.f[0].numpy()
+    fi = WL.uniform_pm1(99, tuple(p.f.shape[1:])).numpy()
+    k2c = p.k2.astype(np.complex128)
+    rc = O.solve("helm4", f + 1j * fi, p.hx, p.hy, p.hz, k2c)
+    rr = O.solve("helm4", f, p.hx, p.hy, p.hz, p.k2)
+    ri = O.solve("helm4", fi, p.hx, p.hy, p.hz, p.k2)
+    assert np.abs(rc.U - (rr.U + 1j * ri.U)).max() <= 1e-13 * np.abs(rc.U).max()
+
+
+@pytest.mark.parametrize("scheme,lo,hi", [("helm4", 3.7, 4.4), ("helm6", 5.5, 6.8)])
+def test_complex_k_observed_order_under_h_halving(scheme, lo, hi):
+    errs = []
+    for n in (15, 31, 63):
+        p = WL.manufactured_sin3(n, n, n, scheme, WL.K_ABSORB)
+        assert np.iscomplexobj(p.k2)
+        res, _, _ = _csolve(p)
+        errs.append(np.abs(res.U - p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1]).max())
+    order = math.log2(errs[1] / errs[2])
+    assert lo < order < hi, (errs, order)

@@ -24,4 +24,6 @@ from .problems import (  # noqa: F401
     config5,
     batch_members,
     noise_problem,
+    complex_noise_problem,
+    K_ABSORB,
 )

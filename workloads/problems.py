@@ -23,7 +23,8 @@ from .gen import gaussian, uniform01, uniform_pm1
 
 @dataclass
 class KProfile:
-    """k(z) with its first two derivatives (all callables on numpy arrays)."""
+    """k(z) with its first two derivatives (all callables on numpy arrays; complex values
+    describe an absorbing medium)."""
 
     k: Callable
     dk: Callable
@@ -35,9 +36,10 @@ class KProfile:
         k2 = k * k
         k2_z = 2.0 * k * dk
         k2_zz = 2.0 * dk * dk + 2.0 * k * d2k
-        return (np.ascontiguousarray(k2, dtype=np.float64),
-                np.ascontiguousarray(k2_z, dtype=np.float64),
-                np.ascontiguousarray(k2_zz, dtype=np.float64))
+        dt = np.complex128 if np.iscomplexobj(k2) else np.float64  # complex k: absorbing media
+        return (np.ascontiguousarray(k2, dtype=dt),
+                np.ascontiguousarray(k2_z, dtype=dt),
+                np.ascontiguousarray(k2_zz, dtype=dt))
 
 
 def k_const(k0):
@@ -244,6 +246,29 @@ def noise_problem(nx, ny, nz, scheme, seed, device="cpu", box=None, gamma=-7.5,
     return Problem(f"noise_{scheme}_{nx}x{ny}x{nz}_s{seed}", scheme, nx, ny, nz, hx, hy, hz,
                    f=f, g_lo=g_lo, g_hi=g_hi, k2=k2, k2_z=k2z, k2_zz=k2zz,
                    gamma=gamma if scheme == "cd4" else 0.0)
+
+
+# absorbing medium: complex k(z) = 6 + 2 sin 3z + i (1 + 0.5 cos 2z)
+K_ABSORB = KProfile(lambda z: (6.0 + 2.0 * np.sin(3.0 * z)) + 1j * (1.0 + 0.5 * np.cos(2.0 * z)),
+                    lambda z: 6.0 * np.cos(3.0 * z) - 1j * np.sin(2.0 * z),
+                    lambda z: -18.0 * np.sin(3.0 * z) - 2j * np.cos(2.0 * z), "6+2 sin 3z + i(1+0.5 cos 2z)")
+
+
+def complex_noise_problem(nx, ny, nz, scheme, seed, device="cpu", boundary=True, nrhs=1, prof=None):
+    """Complex k(z) (absorbing medium, default ``K_ABSORB``), complex random right-hand
+    sides and z-face data (complex128 tensors; real and imaginary parts U[-1, 1])."""
+    p = noise_problem(nx, ny, nz, scheme, seed, device=device, boundary=False, nrhs=nrhs,
+                      prof=K_ABSORB if prof is None else prof)
+    shape = tuple(p.f.shape)
+    p.f = torch.complex(p.f, uniform_pm1(seed + 7, shape, device=device))
+    if boundary:
+        pl = (nrhs, ny + 2, nx + 2)
+        p.g_lo = _zero_ring_(torch.complex(uniform_pm1(seed + 1, pl, device=device),
+                                           uniform_pm1(seed + 8, pl, device=device)))
+        p.g_hi = _zero_ring_(torch.complex(uniform_pm1(seed + 2, pl, device=device),
+                                           uniform_pm1(seed + 9, pl, device=device)))
+    p.name = f"cplx_{scheme}_{nx}x{ny}x{nz}_s{seed}"
+    return p
 
 
 def batch_members(seed=104, count=64, sizes=(63, 127, 255), device="cpu", make_fields=True):
