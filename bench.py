@@ -87,7 +87,7 @@ def measured_traffic(kernel, nrhs):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(p_dev, planes):
+def cpu_baseline(n, planes):
     """Time the oracle (FP64, as it stands) on a slab of `planes` z-planes of one right-hand
     side of the same workload: RHS operator, forward 2-D DST, the Thomas sweep over the
     matching share of modal columns (all N_z planes), inverse 2-D DST."""
@@ -102,8 +102,7 @@ def cpu_baseline(p_dev, planes):
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    n = p_dev.nx
-    P = min(planes, p_dev.nz)
+    P = min(planes, n)
     # the same closed-grid f of right-hand side 0, restricted to planes 0..P+1
     # (counter-based noise: the values are those the device solved)
     prob = WL.config5(n=n, nrhs=1, device="cpu", planes=P + 2)
@@ -208,6 +207,43 @@ def batch_bench(cs3d, dev, steps, warmup):
     return out
 
 
+def complex_bench(cs3d, dev, n, nrhs, steps, warmup):
+    """The same 6th-order workload in an absorbing medium, k = 80(1 + 0.05i) exp(-z):
+    complex tridiagonal solves, real transforms of both parts, planar fields."""
+    import torch
+
+    import workloads as WL
+
+    p = WL.config5_absorbing(n=n, nrhs=nrhs, device=dev)
+    f = torch.stack([p.f.real, p.f.imag], dim=1).contiguous()
+    del p.f
+    torch.cuda.empty_cache()
+    plan = cs3d.plan_for_problem(p, max_rhs=nrhs, device=dev)
+    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        plan.solve(f, out=u)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(f, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = plan.stats()
+    out = {"workload": f"helm6_kexp_absorbing_{n}^3_x{nrhs}complex_rhs", "k": "80 (1 + 0.05i) exp(-z)",
+           "ms_per_step": round(ms, 4), "value": round(nrhs * n ** 3 / (ms / 1e3), 1),
+           "unit": "complex unknowns/s", "stage_ms": [round(x, 4) for x in st["stage_ms"]],
+           "min_abs_pivot": st["min_abs_pivot"], "bad_pivots": st["bad_pivots"]}
+    log(f"[bench] complex k: {ms:.3f} ms per step of {nrhs} complex right-hand sides; stages {out['stage_ms']}")
+    plan.close()
+    del plan, u, f
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +255,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
+    ap.add_argument("--no-complex", action="store_true", help="skip the absorbing-medium (complex k) timing")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune each plan before timing (the defaults are the tuned shapes of this workload)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -296,11 +333,16 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_bench(cs3d, dev, args.steps, args.warmup)
+    cplx = None
+    if not args.no_complex:
+        del p
+        torch.cuda.empty_cache()
+        cplx = complex_bench(cs3d, dev, n, max(1, nrhs // 2), args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_planes} planes")
-        cpu = cpu_baseline(p, args.cpu_planes)
+        cpu = cpu_baseline(n, args.cpu_planes)
         cpu["value"] = round(cpu["value"], 1)
         log(f"[bench] cpu baseline {cpu['value']:.3e} unknowns/s")
 
@@ -319,6 +361,7 @@ def main():
         "paths": paths,
         "fp64_path_algorithmic_GBs": round(whole_gbs, 1),
         "batch": batch,
+        "complex_k": cplx,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -26,6 +26,11 @@
  *    (0-based, boundary included) at i + (nx+2)*(j + (ny+2)*l).  z-face data are
  *    closed planes of (nx+2)*(ny+2) doubles, ring included.
  *  - Several right-hand sides are stored back to back (stride = one array).
+ *  - Complex plans (desc.k2_im != NULL): nrhs counts complex right-hand sides and every
+ *    complex array is planar, the real part followed by the imaginary part, each of the
+ *    documented real shape; so f holds nrhs x 2 closed grids, u nrhs x 2 interior arrays,
+ *    z-face data nrhs x 2 planes (right-hand side r: real part at array 2r, imaginary at
+ *    2r+1).
  *  - Pointers named dev_* are device (HIP) pointers; everything else is host.
  *  - The caller owns every data buffer and the workspace; a plan owns only its
  *    small device tables.  Nothing is allocated during a solve.
@@ -88,6 +93,13 @@ typedef struct {
   int precision;           /* cs3d_precision */
   int refine_steps;        /* mixed precision: number of FP64 residual refinement steps (>= 0) */
   int max_rhs;             /* largest nrhs a solve will be called with (>= 1) */
+  const double* k2_im;     /* host, nz+2 samples of Im k(z)^2, or NULL (real k).  Non-NULL makes
+                              the plan complex (absorbing media; Section 1 allows complex k):
+                              k2 then holds Re k^2, the weights, modal eigenvalues, tridiagonal
+                              solves and every field are complex.  HELM2 / HELM4 / HELM6 with
+                              CS3D_FP64 only (else E_UNSUPPORTED). */
+  const double* k2_z_im;   /* host, nz+2 samples of Im (k^2)_z; complex HELM6 only */
+  const double* k2_zz_im;  /* host, nz+2 samples of Im (k^2)_zz; complex HELM6 only */
 } cs3d_desc;
 
 typedef struct {
@@ -142,7 +154,7 @@ cs3d_status cs3d_solve_assembled(cs3d_plan plan, int nrhs, const double* dev_F, 
 /* FP64 residual of eq. stencil27: dev_r = F - A U over the interior, with F the scheme's
  * RHS operator applied to dev_f (or dev_F itself when dev_f_is_assembled != 0) and the
  * z-face data taking the place of the boundary planes of U.
- * Errors: as cs3d_solve. */
+ * Errors: as cs3d_solve; E_UNSUPPORTED for complex plans. */
 cs3d_status cs3d_residual(cs3d_plan plan, int nrhs, const double* dev_f, int dev_f_is_assembled,
                           const double* dev_g_lo, const double* dev_g_hi, const double* dev_u,
                           double* dev_r, void* hip_stream);
@@ -197,7 +209,8 @@ cs3d_status cs3d_autotune(cs3d_plan plan, int nrhs, const double* dev_f, const d
 
 /* Batches: n independent problems, each with its own sizes, steps, scheme and
  * coefficients (desc[i]; max_rhs is ignored, every member takes one right-hand side,
- * precision must be CS3D_FP64, scheme must not be CS3D_WEIGHTS), solved together.  Every
+ * precision must be CS3D_FP64, k must be real, scheme must not be CS3D_WEIGHTS), solved
+ * together.  Every
  * pass of Section 3.6 (RHS operator and lift, x-DST, y-DST with forward elimination, back
  * substitution with inverse y-DST, inverse x-DST) is ONE launch over the work items of all
  * members (tiles, line groups), taken by a resident set of workgroups from a device work
@@ -205,7 +218,7 @@ cs3d_status cs3d_autotune(cs3d_plan plan, int nrhs, const double* dev_f, const d
  * goes through the per-item code of a plan built from its desc (default y-line split).
  * The z-face data are zero.
  * Errors: E_INVAL (n < 1, NULL pointers, a desc rejected by cs3d_plan_create or
- * CS3D_WEIGHTS), E_UNSUPPORTED (mixed precision), E_NOMEM, E_DEVICE. */
+ * CS3D_WEIGHTS), E_UNSUPPORTED (mixed precision, complex k), E_NOMEM, E_DEVICE. */
 cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hip_stream, cs3d_batch* out);
 
 /* Bytes of device workspace of the batch (the members' workspaces back to back). */

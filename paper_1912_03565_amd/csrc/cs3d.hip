@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -84,22 +85,32 @@ struct cs3d_plan_s {
   int cur_marks = 0;
   int refine_done = 0;
   std::vector<double> hW;  // host copy of the weights
+  // complex k: imaginary parts of the weights, modal coefficients and k^2 samples
+  bool cplx = false;
+  double* dWi = nullptr;
+  double* dLCi = nullptr;
+  double* dk2i = nullptr;
+  double* dk2zi = nullptr;
 };
 
 // ---------------------------------------------------------------------------
 // Row weights, Sections 3.2 - 3.5.  W[l][o][(a,b,c,d)], o = 0,1,2 for offsets -1,0,+1.
 // ---------------------------------------------------------------------------
-static cs3d_status build_weights(const cs3d_desc& d, std::vector<double>& W) {
+// S = double, or std::complex<double> for complex k (absorbing media): the same formulas
+// with complex k^2 samples k2s, k2zs, k2zzs (nz+2 each)
+template <typename S>
+static cs3d_status build_weights_t(const cs3d_desc& d, const S* k2s, const S* k2zs, const S* k2zzs,
+                                   std::vector<S>& W) {
   const int nz = d.nz;
-  W.assign((size_t)nz * 12, 0.0);
+  W.assign((size_t)nz * 12, S(0.0));
   const double rzx = d.hz * d.hz / (d.hx * d.hx), rzy = d.hz * d.hz / (d.hy * d.hy);
   const double hz2 = d.hz * d.hz;
-  auto at = [&](int l, int o, int q) -> double& { return W[(size_t)l * 12 + o * 4 + q]; };
+  auto at = [&](int l, int o, int q) -> S& { return W[(size_t)l * 12 + o * 4 + q]; };
   for (int l = 0; l < nz; ++l) {
     const int zl = l + 1;  // sample index of plane z_l
     switch (d.scheme) {
       case CS3D_HELM2: {
-        const double k0 = d.k2[zl];
+        const S k0 = k2s[zl];
         at(l, 0, 3) = 1.0;
         at(l, 2, 3) = 1.0;
         at(l, 1, 1) = rzx;
@@ -108,9 +119,9 @@ static cs3d_status build_weights(const cs3d_desc& d, std::vector<double>& W) {
         break;
       }
       case CS3D_HELM4: {
-        const double km = d.k2[zl - 1], k0 = d.k2[zl], kp = d.k2[zl + 1];
+        const S km = k2s[zl - 1], k0 = k2s[zl], kp = k2s[zl + 1];
         for (int o = 0; o <= 2; o += 2) {
-          const double kk = o == 0 ? km : kp;
+          const S kk = o == 0 ? km : kp;
           at(l, o, 1) = (1.0 + rzx) / 12.0;
           at(l, o, 2) = (1.0 + rzy) / 12.0;
           at(l, o, 3) = 2.0 / 3.0 - (rzx + rzy) / 6.0 + hz2 * kk / 12.0;
@@ -123,12 +134,13 @@ static cs3d_status build_weights(const cs3d_desc& d, std::vector<double>& W) {
       }
       case CS3D_HELM6: {
         const double h = d.hz, h2 = h * h, h3 = h2 * h, h4 = h2 * h2;
-        const double km = d.k2[zl - 1], k0 = d.k2[zl], kp = d.k2[zl + 1];
-        const double kz = d.k2_z[zl], kzz = d.k2_zz[zl];
+        const S km = k2s[zl - 1], k0 = k2s[zl], kp = k2s[zl + 1];
+        const S kz = k2zs[zl], kzz = k2zzs[zl];
         for (int o = 0; o <= 2; o += 2) {
-          const double sg = o == 0 ? -1.0 : 1.0, kk = o == 0 ? km : kp;
+          const double sg = o == 0 ? -1.0 : 1.0;
+          const S kk = o == 0 ? km : kp;
           at(l, o, 0) = 1.0 / 30.0;
-          const double bc = 0.1 + h2 * kk / 90.0 + sg * h3 * kz / 120.0;
+          const S bc = 0.1 + h2 * kk / 90.0 + sg * h3 * kz / 120.0;
           at(l, o, 1) = bc;
           at(l, o, 2) = bc;
           at(l, o, 3) = 7.0 / 15.0 - h2 * kk / 90.0 + sg * (h3 * kz / 20.0) * (1.0 / 3.0 + h2 * kk / 6.0);
@@ -154,13 +166,36 @@ static cs3d_status build_weights(const cs3d_desc& d, std::vector<double>& W) {
         break;
       }
       case CS3D_WEIGHTS:
-        for (int q = 0; q < 12; ++q) W[(size_t)l * 12 + q] = d.weights[(size_t)l * 12 + q];
+        for (int q = 0; q < 12; ++q) W[(size_t)l * 12 + q] = S(d.weights[(size_t)l * 12 + q]);
         break;
       default:
         return CS3D_E_INVAL;
     }
   }
   return CS3D_OK;
+}
+
+static cs3d_status build_weights(const cs3d_desc& d, std::vector<double>& W) {
+  return build_weights_t<double>(d, d.k2, d.k2_z, d.k2_zz, W);
+}
+
+// complex k: weights of (Re k^2 + i Im k^2), split into real and imaginary tables
+static cs3d_status build_weights_c(const cs3d_desc& d, std::vector<double>& Wr, std::vector<double>& Wi) {
+  const int nzp = d.nz + 2;
+  std::vector<std::complex<double>> k2(nzp), k2z(nzp, 0.0), k2zz(nzp, 0.0), W;
+  for (int i = 0; i < nzp; ++i) {
+    k2[i] = {d.k2[i], d.k2_im[i]};
+    if (d.k2_z) k2z[i] = {d.k2_z[i], d.k2_z_im ? d.k2_z_im[i] : 0.0};
+    if (d.k2_zz) k2zz[i] = {d.k2_zz[i], d.k2_zz_im ? d.k2_zz_im[i] : 0.0};
+  }
+  const cs3d_status st = build_weights_t<std::complex<double>>(d, k2.data(), k2z.data(), k2zz.data(), W);
+  Wr.resize(W.size());
+  Wi.resize(W.size());
+  for (size_t q = 0; q < W.size(); ++q) {
+    Wr[q] = W[q].real();
+    Wi[q] = W[q].imag();
+  }
+  return st;
 }
 
 // exp(-i pi k/M), k < 2M; angles reduced exactly (k is an integer < 2M)
@@ -205,6 +240,23 @@ static void modal_coefficients(const std::vector<double>& W, std::vector<double>
   }
 }
 
+// the same coefficients for complex weights (Wr + i Wi), real and imaginary parts
+static void modal_coefficients_c(const std::vector<double>& Wr, const std::vector<double>& Wi,
+                                 std::vector<double>& LCr, std::vector<double>& LCi) {
+  LCr.resize(Wr.size());
+  LCi.resize(Wr.size());
+  for (size_t r = 0; r < Wr.size() / 4; ++r) {
+    using C = std::complex<long double>;
+    const C a(Wr[4 * r], Wi[4 * r]), b(Wr[4 * r + 1], Wi[4 * r + 1]), c(Wr[4 * r + 2], Wi[4 * r + 2]),
+        d(Wr[4 * r + 3], Wi[4 * r + 3]);
+    const C v[4] = {4.0L * a + 2.0L * b + 2.0L * c + d, -(4.0L * a + 2.0L * b), -(4.0L * a + 2.0L * c), 4.0L * a};
+    for (int q = 0; q < 4; ++q) {
+      LCr[4 * r + q] = (double)v[q].real();
+      LCi[4 * r + q] = (double)v[q].imag();
+    }
+  }
+}
+
 static cs3d_status validate(const cs3d_desc* d) {
   if (!d) return CS3D_E_INVAL;
   if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > kMaxN || d->ny > kMaxN) return CS3D_E_INVAL;
@@ -234,12 +286,18 @@ static cs3d_status validate(const cs3d_desc* d) {
     default:
       return CS3D_E_INVAL;
   }
+  if (d->k2_im) {  // complex k: Helmholtz schemes, FP64
+    if (d->scheme == CS3D_HELM6 && (!d->k2_z_im || !d->k2_zz_im)) return CS3D_E_INVAL;
+    if (d->scheme != CS3D_HELM2 && d->scheme != CS3D_HELM4 && d->scheme != CS3D_HELM6) return CS3D_E_UNSUPPORTED;
+    if (d->precision != CS3D_FP64) return CS3D_E_UNSUPPORTED;
+  }
   return CS3D_OK;
 }
 
 static void plan_free(cs3d_plan p) {
   if (!p) return;
-  void* ptrs[] = {p->dW, p->dLC, p->dk2, p->dk2z, p->dctx, p->dcty, p->dtwx, p->dtwy, p->dsinx, p->dsiny, p->dstats};
+  void* ptrs[] = {p->dW,   p->dLC,  p->dk2,    p->dk2z, p->dctx, p->dcty, p->dtwx, p->dtwy,
+                  p->dsinx, p->dsiny, p->dstats, p->dWi,  p->dLCi, p->dk2i, p->dk2zi};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t e : p->ring)
@@ -267,6 +325,8 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   if (!p) return CS3D_E_NOMEM;
   p->d = *desc;
   p->d.k2 = p->d.k2_z = p->d.k2_zz = p->d.weights = nullptr;  // host arrays are not kept
+  p->d.k2_im = p->d.k2_z_im = p->d.k2_zz_im = nullptr;
+  p->cplx = desc->k2_im != nullptr;
   p->Mx = desc->nx + 1;
   p->My = desc->ny + 1;
   p->fx = fft_len(desc->nx);
@@ -278,7 +338,8 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   const bool mixed = desc->precision != CS3D_FP64;
   p->tune.zchunk = desc->nz >= 512 ? (mixed ? 128 : 64) : kZChunk;
   p->tune.yrhs = mixed ? 2 : 1;
-  st = build_weights(*desc, p->hW);
+  std::vector<double> hWi;
+  st = p->cplx ? build_weights_c(*desc, p->hW, hWi) : build_weights(*desc, p->hW);
   if (st != CS3D_OK) {
     plan_free(p);
     return st;
@@ -290,11 +351,17 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
     for (int i = 0; i < nzp; ++i) k2[i] = desc->k2[i];
   if (desc->k2_z)
     for (int i = 0; i < nzp; ++i) k2z[i] = desc->k2_z[i];
-  std::vector<double> ctx, cty, sx, sy, lc;
+  std::vector<double> ctx, cty, sx, sy, lc, lci, k2i(nzp, 0.0), k2zi(nzp, 0.0);
+  if (p->cplx) {
+    for (int i = 0; i < nzp; ++i) k2i[i] = desc->k2_im[i];
+    if (desc->k2_z_im)
+      for (int i = 0; i < nzp; ++i) k2zi[i] = desc->k2_z_im[i];
+  }
   std::vector<double2> twx, twy;
   one_minus_cosines(desc->nx, ctx);
   one_minus_cosines(desc->ny, cty);
-  modal_coefficients(p->hW, lc);
+  if (p->cplx) modal_coefficients_c(p->hW, hWi, lc, lci);
+  else modal_coefficients(p->hW, lc);
   twiddles(p->Mx, twx);
   twiddles(p->My, twy);
   sines(p->Mx, sx);
@@ -310,6 +377,16 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   CS3D_TRY(dalloc(&p->dsinx, sx.size()));
   CS3D_TRY(dalloc(&p->dsiny, sy.size()));
   CS3D_TRY(dalloc(&p->dstats, kStatsWords));
+  if (p->cplx) {
+    CS3D_TRY(dalloc(&p->dWi, hWi.size()));
+    CS3D_TRY(dalloc(&p->dLCi, lci.size()));
+    CS3D_TRY(dalloc(&p->dk2i, k2i.size()));
+    CS3D_TRY(dalloc(&p->dk2zi, k2zi.size()));
+    CS3D_TRY(hipMemcpyAsync(p->dWi, hWi.data(), hWi.size() * 8, hipMemcpyHostToDevice, s));
+    CS3D_TRY(hipMemcpyAsync(p->dLCi, lci.data(), lci.size() * 8, hipMemcpyHostToDevice, s));
+    CS3D_TRY(hipMemcpyAsync(p->dk2i, k2i.data(), k2i.size() * 8, hipMemcpyHostToDevice, s));
+    CS3D_TRY(hipMemcpyAsync(p->dk2zi, k2zi.data(), k2zi.size() * 8, hipMemcpyHostToDevice, s));
+  }
   CS3D_TRY(hipMemcpyAsync(p->dW, p->hW.data(), p->hW.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipMemcpyAsync(p->dLC, lc.data(), lc.size() * 8, hipMemcpyHostToDevice, s));
   CS3D_TRY(hipMemcpyAsync(p->dk2, k2.data(), k2.size() * 8, hipMemcpyHostToDevice, s));
@@ -347,10 +424,18 @@ static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static size_t n3(const cs3d_plan p) { return (size_t)p->d.nx * p->d.ny * p->d.nz; }
 
-// workspace layout: G (transform intermediate, per rhs) | C (c' of the LU, shared by the
-// right-hand sides) | mixed path only: F (FP64 right-hand side, per rhs) | R (FP64 residual)
-static size_t off_C(const cs3d_plan p, int nrhs) { return round256(g_elems(p) * elem_bytes(p) * (size_t)nrhs); }
-static size_t off_F(const cs3d_plan p, int nrhs) { return off_C(p, nrhs) + round256(g_elems(p) * 8); }
+// real slots of nrhs right-hand sides (two per complex right-hand side)
+static int slots(const cs3d_plan p, int nrhs) { return p->cplx ? 2 * nrhs : nrhs; }
+
+// workspace layout: G (transform intermediate, per real slot) | C (c' of the LU, shared by
+// the right-hand sides; real and imaginary parts for complex k) | mixed path only:
+// F (FP64 right-hand side, per rhs) | R (FP64 residual)
+static size_t off_C(const cs3d_plan p, int nrhs) {
+  return round256(g_elems(p) * elem_bytes(p) * (size_t)slots(p, nrhs));
+}
+static size_t off_F(const cs3d_plan p, int nrhs) {
+  return off_C(p, nrhs) + round256(g_elems(p) * 8 * (p->cplx ? 2 : 1));
+}
 static size_t off_R(const cs3d_plan p, int nrhs) { return off_F(p, nrhs) + round256(n3(p) * 8 * (size_t)nrhs); }
 
 extern "C" size_t cs3d_workspace_bytes(cs3d_plan p, int nrhs) {
@@ -572,6 +657,13 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) + off_C(p, nrhs)) : nullptr;
   pd.stats = p->dstats;
   pd.zchunk = p->tune.zchunk;
+  if (p->cplx) {
+    pd.Wi = p->dWi;
+    pd.LCi = p->dLCi;
+    pd.k2i = p->dk2i;
+    pd.k2zi = p->dk2zi;
+    pd.Ci = pd.C ? pd.C + g_elems(p) : nullptr;
+  }
   return pd;
 }
 
@@ -620,6 +712,49 @@ static hipError_t transform_solve(cs3d_plan p, const ProbDev& pd, int nrhs, hipS
   return run_x_inv<T>(p, pd, nrhs, s);
 }
 
+// complex k: the y passes carry both real slots of each complex right-hand side
+template <int MY>
+static hipError_t run_y_c_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s, bool fwd) {
+  constexpr int WPL = default_wpl<MY>();
+  const dim3 grid((p->d.nx + YCfg<MY, WPL>::LPB - 1) / YCfg<MY, WPL>::LPB, nrhs);
+  const size_t lds = lds_bytes_y_t<double, MY, WPL>(p);
+  return fwd ? launch(k_fwd_y_c<MY, WPL>, grid, dim3(kBlockY), lds, s, pd)
+             : launch(k_back_y_c<MY, WPL>, grid, dim3(kBlockY), lds, s, pd);
+}
+
+static hipError_t run_y_c(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s, bool fwd) {
+  switch (p->fy) {
+    case 64: return run_y_c_t<64>(p, pd, nrhs, s, fwd);
+    case 128: return run_y_c_t<128>(p, pd, nrhs, s, fwd);
+    case 256: return run_y_c_t<256>(p, pd, nrhs, s, fwd);
+    case 512: return run_y_c_t<512>(p, pd, nrhs, s, fwd);
+    case 1024: return run_y_c_t<1024>(p, pd, nrhs, s, fwd);
+    default: return run_y_c_t<0>(p, pd, nrhs, s, fwd);
+  }
+}
+
+// K1 -> K2 -> K3 -> K4 for nrhs complex right-hand sides (FP64)
+static hipError_t transform_solve_c(cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  hipError_t e;
+  if ((e = mark(p, 1, s)) != hipSuccess) return e;
+  if ((e = run_x_fwd<double>(p, pd, 2 * nrhs, s)) != hipSuccess) return e;
+  if ((e = mark(p, 2, s)) != hipSuccess) return e;
+  if ((e = run_y_c(p, pd, nrhs, s, true)) != hipSuccess) return e;
+  if ((e = mark(p, 3, s)) != hipSuccess) return e;
+  if ((e = run_y_c(p, pd, nrhs, s, false)) != hipSuccess) return e;
+  if ((e = mark(p, 4, s)) != hipSuccess) return e;
+  return run_x_inv<double>(p, pd, 2 * nrhs, s);
+}
+
+// complex k: the terms of the RHS operator and the lift that couple the two parts
+static hipError_t run_rhs_cx(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  const bool h6 = p->d.scheme == CS3D_HELM6;
+  if (!h6 && !pd.glo && !pd.ghi) return hipSuccess;
+  const dim3 grid((p->d.nx * p->d.ny + 255) / 256, h6 ? p->d.nz : (p->d.nz == 1 ? 1 : 2), nrhs);
+  hipLaunchKernelGGL(k_rhs_cx, grid, dim3(256), 0, s, pd);
+  return hipGetLastError();
+}
+
 static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s);
 
 // r = F - A U and its squared norm into stats word `slot` (slot < 0: no norm)
@@ -656,11 +791,15 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   hipLaunchKernelGGL(k_stats_reset, dim3(1), dim3(64), 0, s, p->dstats);
   if (hipGetLastError() != hipSuccess) return CS3D_E_DEVICE;
   if (!assembled) {
-    if (mark(p, 0, s) != hipSuccess || run_rhs(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+    if (mark(p, 0, s) != hipSuccess || run_rhs(p, pd, slots(p, nrhs), s) != hipSuccess) return CS3D_E_DEVICE;
+    if (p->cplx && run_rhs_cx(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
   }
   pd.u = u;
   pd.accumulate = 0;
-  if (!mixed) {
+  if (p->cplx) {
+    if (transform_solve_c(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
+    p->refine_done = 0;
+  } else if (!mixed) {
     if (transform_solve<double>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
     p->refine_done = 0;
   } else {
@@ -713,6 +852,7 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
   if (dev_r == dev_u || dev_r == dev_f) return CS3D_E_INVAL;
+  if (p->cplx) return CS3D_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)hip_stream;
   // F (with the lift) goes into r, then r = F - A U in place
   const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
@@ -1108,7 +1248,7 @@ extern "C" cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hi
     const cs3d_status st = validate(&d);
     if (st != CS3D_OK) return st;
     if (d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
-    if (d.precision != CS3D_FP64) return CS3D_E_UNSUPPORTED;
+    if (d.precision != CS3D_FP64 || d.k2_im) return CS3D_E_UNSUPPORTED;
   }
   cs3d_batch b = new (std::nothrow) cs3d_batch_s();
   if (!b) return CS3D_E_NOMEM;

@@ -62,6 +62,13 @@ struct ProbDev {
   unsigned long long* stats;  // [0] = bits of min |pivot|, [1] = count of bad pivots
   int accumulate;      // K4: u += result (refinement corrections) instead of u = result
   int zchunk;          // planes per workgroup of the z-marching passes (K0, residual)
+  // complex k (absorbing media): imaginary parts; a complex right-hand side q occupies the
+  // real slots 2q (real part) and 2q+1 (imaginary part) of f, F, u, G and the z-face data
+  const double* Wi;    // [nz][3][4] imaginary parts of the row weights
+  const double* LCi;   // [nz][3][4] imaginary parts of (Z, B, C, A)
+  const double* k2i;   // [nz+2] Im k^2
+  const double* k2zi;  // [nz+2] Im (k^2)_z
+  double* Ci;          // [nz][nx][ldy] Im c'
 };
 
 // ---------------------------------------------------------------------------
@@ -781,6 +788,236 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Complex k (absorbing media).  The sine transforms are real, so K0 (per real slot,
+// with Re k^2 and the real weights), K1 and K4 run unchanged over the 2 nrhs real
+// slots; k_rhs_cx adds the terms that couple the real and imaginary parts, and the
+// y passes carry both slots of a complex right-hand side and solve the complex
+// tridiagonal systems.
+// ---------------------------------------------------------------------------
+
+// F of complex right-hand side q at the planes it touches: the Im k^2 terms of the
+// 6th-order operator (every plane) and the Im W terms of the z-face lift (planes 1, nz).
+// grid: (ceil(nx ny / 256), planes, complex right-hand sides)
+__global__ void __launch_bounds__(256) k_rhs_cx(ProbDev p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.nx * p.ny) return;
+  const int i = 1 + e % p.nx, j = 1 + e / p.nx;
+  const bool h6 = p.scheme == kHelm6;
+  const int l = h6 ? 1 + (int)blockIdx.y : (blockIdx.y == 0 ? 1 : p.nz);
+  const int q = blockIdx.z;
+  const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
+  const long long idx = (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+  double dre = 0.0, dim = 0.0;  // corrections of Re F and Im F
+  if (h6 && p.f) {
+    const double* fr = p.f + (2 * q) * p.f_stride + i + sy * j + sz * l;
+    const double* fi = fr + p.f_stride;
+    const double h = p.hz, hz2 = h * h;
+    const double ki = p.k2i[l], kzi = p.k2zi[l];
+    // -(h^2/20) k^2 f + (h^3/120) (k^2)_z (f_{l+1} - f_{l-1}), imaginary-part products
+    dre = hz2 * (h * h * ki * fi[0] * (1.0 / 20.0) - h * h * h * kzi * (fi[sz] - fi[-sz]) * (1.0 / 120.0));
+    dim = hz2 * (-h * h * ki * fr[0] * (1.0 / 20.0) + h * h * h * kzi * (fr[sz] - fr[-sz]) * (1.0 / 120.0));
+  }
+  // lift: F -= W g with complex W and g; the real parts were lifted per slot
+  if (l == 1 && p.glo) {
+    const double* gr = p.glo + (2 * q) * p.g_stride;
+    dre += plane9(p.Wi + 0, gr + p.g_stride, p.nx, i, j);
+    dim -= plane9(p.Wi + 0, gr, p.nx, i, j);
+  }
+  if (l == p.nz && p.ghi) {
+    const double* gr = p.ghi + (2 * q) * p.g_stride;
+    const double* w = p.Wi + (p.nz - 1) * 12 + 8;
+    dre += plane9(w, gr + p.g_stride, p.nx, i, j);
+    dim -= plane9(w, gr, p.nx, i, j);
+  }
+  double* u = p.u + (2 * q) * p.u_stride + idx;
+  u[0] += dre;
+  u[p.u_stride] += dim;
+}
+
+__device__ __forceinline__ void record_pivot_c(double pr, double pi, double& minpiv, unsigned& bad) {
+  const double a = hypot(pr, pi);
+  if (!(a > 0.0) || !isfinite(a)) {
+    ++bad;
+  } else if (a < minpiv) {
+    minpiv = a;
+  }
+}
+
+// y-DST of the two slots of complex right-hand side q, complex modal eigenvalues and
+// forward elimination (FP64 transforms)
+template <int MY, int WPL>
+__device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, double* smem, const cx<double>* tab) {
+  using C = YCfg<MY, WPL>;
+  constexpr int NS = C::NS;
+  const int bufn = line_buf_elems<double, MY, WPL>(p.ny);
+  const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
+  const int n = g * C::LPB + line + 1;
+  const bool active = n <= p.nx;
+  if constexpr (WPL == 1) {
+    if (!active) return;
+  }
+  double* buf = smem + line * bufn;
+  const double ctn = active ? p.ctx[n - 1] : 0.0;
+  double cpr[NS], cpi[NS], dpr[NS], dpi[NS], orr[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) cpr[s] = cpi[s] = dpr[s] = dpi[s] = 0.0;
+  double minpiv = 1.0e308;
+  unsigned bad = 0;
+  const bool lead = (q == 0);
+  const long long lstride = (long long)p.nx * p.ldy;
+  const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
+  double* G0 = reinterpret_cast<double*>(p.G) + (2 * q) * p.G_stride;
+  double pre[C::NLD];
+  auto fetch = [&](int l, int part) {
+    const double* src = G0 + part * p.G_stride + (long long)(l - 1) * lstride + nbase + opaque(tl);
+#pragma unroll
+    for (int s = 0; s < C::NLD; ++s) pre[s] = (active && tl + C::LANES * s <= p.ny) ? src[C::LANES * s] : 0.0;
+  };
+  fetch(1, 0);
+  for (int l = 1; l <= p.nz; ++l) {
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+      for (int s = 0; s < C::NLD; ++s) {
+        const int e = tl + C::LANES * s;
+        if (e <= p.ny) buf[e] = pre[s];
+      }
+      line_sync<WPL>();
+      if (part == 0) fetch(l, 1);
+      else if (l < p.nz) fetch(l + 1, 0);
+      double out[NS];
+      line_dst<double, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      if (part == 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) orr[s] = out[s];
+      } else if (active) {
+        const double* Lr = p.LC + (l - 1) * 12;
+        const double* Li = p.LCi + (l - 1) * 12;
+        double* Cr = p.C + (long long)(l - 1) * lstride + nbase;
+        double* Cim = p.Ci + (long long)(l - 1) * lstride + nbase;
+        double* d0 = G0 + (long long)(l - 1) * lstride + nbase;
+        double* d1 = d0 + p.G_stride;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int m = line_mode<MY, WPL>(tl, s, p.ny);
+          if (m > 0) {
+            const double sm = p.cty[m - 1];
+            // lambda^o = (Z + s_n B) + s_m (C + A s_n), real and imaginary parts
+            const double lmr = (Lr[2] + Lr[3] * ctn) * sm + (Lr[0] + ctn * Lr[1]);
+            const double lmi = (Li[2] + Li[3] * ctn) * sm + (Li[0] + ctn * Li[1]);
+            const double l0r = (Lr[6] + Lr[7] * ctn) * sm + (Lr[4] + ctn * Lr[5]);
+            const double l0i = (Li[6] + Li[7] * ctn) * sm + (Li[4] + ctn * Li[5]);
+            const double lpr = (Lr[10] + Lr[11] * ctn) * sm + (Lr[8] + ctn * Lr[9]);
+            const double lpi = (Li[10] + Li[11] * ctn) * sm + (Li[8] + ctn * Li[9]);
+            // pivot = l0 - lm c'
+            const double pr = l0r - (lmr * cpr[s] - lmi * cpi[s]);
+            const double pim = l0i - (lmr * cpi[s] + lmi * cpr[s]);
+            if (lead) record_pivot_c(pr, pim, minpiv, bad);
+            const double den = 1.0 / (pr * pr + pim * pim);
+            const double ir = pr * den, ii = -pim * den;  // 1 / pivot
+            const double ncr = lpr * ir - lpi * ii, nci = lpr * ii + lpi * ir;
+            // d' = (F - lm d'_prev) / pivot
+            const double tr = orr[s] - (lmr * dpr[s] - lmi * dpi[s]);
+            const double ti = out[s] - (lmr * dpi[s] + lmi * dpr[s]);
+            dpr[s] = tr * ir - ti * ii;
+            dpi[s] = tr * ii + ti * ir;
+            cpr[s] = ncr;
+            cpi[s] = nci;
+            d0[m] = dpr[s];
+            d1[m] = dpi[s];
+            if (lead) {
+              Cr[m] = ncr;
+              Cim[m] = nci;
+            }
+          }
+        }
+      }
+      line_sync<WPL>();
+    }
+  }
+  if (lead && (active || WPL > 1)) flush_stats(p, minpiv, bad);
+}
+
+template <int MY, int WPL = default_wpl<MY>()>
+__global__ void __launch_bounds__(kBlockY) k_fwd_y_c(ProbDev p) {
+  extern __shared__ double smem_raw[];
+  const cx<double>* tab = y_tables<double, MY, WPL>(p, smem_raw, true);
+  yfwd_block_c<MY, WPL>(p, blockIdx.x, blockIdx.y, smem_raw, tab);
+}
+
+// complex back substitution, then the inverse y-DST of both slots
+template <int MY, int WPL>
+__device__ __forceinline__ void yback_block_c(const ProbDev& p, int g, int q, double* smem, const cx<double>* tab) {
+  using C = YCfg<MY, WPL>;
+  constexpr int NS = C::NS;
+  const int bufn = line_buf_elems<double, MY, WPL>(p.ny);
+  const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
+  const int n = g * C::LPB + line + 1;
+  const bool active = n <= p.nx;
+  if constexpr (WPL == 1) {
+    if (!active) return;
+  }
+  double* buf = smem + line * bufn;
+  double wr[NS], wi[NS], pdr[NS], pdi[NS], pcr[NS], pci[NS];
+  int mpos[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    mpos[s] = active ? line_mode<MY, WPL>(tl, s, p.ny) : -1;
+    wr[s] = wi[s] = 0.0;
+  }
+  double* G0 = reinterpret_cast<double*>(p.G) + (2 * q) * p.G_stride;
+  const long long lstride = (long long)p.nx * p.ldy;
+  const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
+  auto fetch = [&](int l) {
+    const long long o = (long long)(l - 1) * lstride + nbase;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const bool v = mpos[s] > 0;
+      pdr[s] = v ? G0[o + mpos[s]] : 0.0;
+      pdi[s] = v ? G0[p.G_stride + o + mpos[s]] : 0.0;
+      pcr[s] = v ? p.C[o + mpos[s]] : 0.0;
+      pci[s] = v ? p.Ci[o + mpos[s]] : 0.0;
+    }
+  };
+  fetch(p.nz);
+  for (int l = p.nz; l >= 1; --l) {
+    // W_l = d'_l - c'_l W_{l+1}
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (mpos[s] > 0) {
+        const double nr = pdr[s] - (pcr[s] * wr[s] - pci[s] * wi[s]);
+        const double ni = pdi[s] - (pcr[s] * wi[s] + pci[s] * wr[s]);
+        wr[s] = nr;
+        wi[s] = ni;
+      }
+    }
+    if (l > 1) fetch(l - 1);
+    double* line0 = G0 + (long long)(l - 1) * lstride + nbase;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (mpos[s] > 0) buf[mpos[s]] = part == 0 ? wr[s] : wi[s];
+      line_sync<WPL>();
+      double out[NS];
+      line_dst<double, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      double* dst = line0 + part * p.G_stride;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (mpos[s] > 0) dst[mpos[s]] = out[s];
+      line_sync<WPL>();
+    }
+  }
+}
+
+template <int MY, int WPL = default_wpl<MY>()>
+__global__ void __launch_bounds__(kBlockY) k_back_y_c(ProbDev p) {
+  extern __shared__ double smem_raw[];
+  const cx<double>* tab = y_tables<double, MY, WPL>(p, smem_raw, true);
+  yback_block_c<MY, WPL>(p, blockIdx.x, blockIdx.y, smem_raw, tab);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,6 +39,9 @@ class Desc(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("refine_steps", ctypes.c_int),
         ("max_rhs", ctypes.c_int),
+        ("k2_im", ctypes.POINTER(ctypes.c_double)),
+        ("k2_z_im", ctypes.POINTER(ctypes.c_double)),
+        ("k2_zz_im", ctypes.POINTER(ctypes.c_double)),
     ]
 
 

@@ -54,8 +54,15 @@ def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, g
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.hx, d.hy, d.hz = float(hx), float(hy), float(hz)
     d.scheme = N.SCHEMES[scheme]
-    for field, arr, n in (("k2", k2, nz + 2), ("k2_z", k2_z, nz + 2), ("k2_zz", k2_zz, nz + 2),
-                          ("weights", weights, nz * 12)):
+    # complex k (absorbing media): real parts in k2..., imaginary parts in k2..._im
+    cplx = k2 is not None and np.iscomplexobj(np.asarray(k2))
+    fields = [("k2", k2, nz + 2), ("k2_z", k2_z, nz + 2), ("k2_zz", k2_zz, nz + 2), ("weights", weights, nz * 12)]
+    if cplx:
+        fields = [(nm, None if arr is None else np.real(np.asarray(arr)), n) for nm, arr, n in fields[:3]]
+        fields += [(nm + "_im", None if arr is None else np.imag(np.asarray(arr)), nz + 2)
+                   for nm, arr in (("k2", k2), ("k2_z", k2_z), ("k2_zz", k2_zz))]
+        fields.append(("weights", weights, nz * 12))
+    for field, arr, n in fields:
         a, ptr = _host_array(arr, n, field)
         keep.append(a)
         if ptr is not None:
@@ -76,6 +83,8 @@ class Plan:
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.scheme = scheme
         self.precision = precision
+        # complex k: every field is planar, (nrhs, 2, ...) = real and imaginary parts
+        self.complex = k2 is not None and bool(np.iscomplexobj(np.asarray(k2)))
         self.max_rhs = int(max_rhs)
         self.device = torch.device(device)
         d, keep = _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2, k2_z, k2_zz, gamma, weights,
@@ -89,18 +98,22 @@ class Plan:
             N.check("cs3d_set_workspace", N.lib.cs3d_set_workspace(self._plan, ptr, self.ws_bytes))
 
     # shapes --------------------------------------------------------------
+    def _lead(self, nrhs):
+        return (nrhs, 2) if self.complex else (nrhs,)
+
     def closed_shape(self, nrhs):
-        return (nrhs, self.nz + 2, self.ny + 2, self.nx + 2)
+        return self._lead(nrhs) + (self.nz + 2, self.ny + 2, self.nx + 2)
 
     def interior_shape(self, nrhs):
-        return (nrhs, self.nz, self.ny, self.nx)
+        return self._lead(nrhs) + (self.nz, self.ny, self.nx)
 
     def plane_shape(self, nrhs):
-        return (nrhs, self.ny + 2, self.nx + 2)
+        return self._lead(nrhs) + (self.ny + 2, self.nx + 2)
 
     def _nrhs(self, t):
-        if t.dim() != 4:
-            raise ValueError("expected a 4-D tensor [nrhs, z, y, x]")
+        if t.dim() != (5 if self.complex else 4):
+            raise ValueError("expected a tensor [nrhs, 2, z, y, x] (complex k: real and imaginary parts)"
+                             if self.complex else "expected a 4-D tensor [nrhs, z, y, x]")
         nrhs = t.shape[0]
         if not 1 <= nrhs <= self.max_rhs:
             raise ValueError(f"nrhs must be in [1, {self.max_rhs}], got {nrhs}")

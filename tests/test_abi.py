@@ -143,3 +143,29 @@ def test_tuning_cache_store_and_load(tmp_path, monkeypatch):
     assert tuning.load() == {}  # a damaged cache is ignored, not fatal
     monkeypatch.setenv("CS3D_AUTOTUNE", "0")
     assert not tuning.enabled()
+
+
+@pytest.mark.parametrize("case", ["cd4", "mixed", "helm6_missing_im", "batch"])
+def test_complex_k_validation(N, case):
+    d = _desc(N, n=(63, 63, 63))
+    im = np.full(d.nz + 2, 0.5)
+    d._keep.append(im)
+    ptr = im.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.k2_im = ptr
+    if case != "helm6_missing_im":
+        d.k2_z_im = d.k2_zz_im = ptr
+    want = N.E_UNSUPPORTED
+    if case == "cd4":
+        d.scheme = N.SCHEMES["cd4"]
+    elif case == "mixed":
+        d.precision = N.PRECISIONS["mixed"]
+    elif case == "helm6_missing_im":
+        want = N.E_INVAL
+    if case == "batch":
+        descs = (N.Desc * 1)(d)
+        b = ctypes.c_void_p()
+        assert N.lib.cs3d_batch_create(1, descs, None, ctypes.byref(b)) == want
+        return
+    plan = ctypes.c_void_p()
+    assert N.lib.cs3d_plan_create(ctypes.byref(d), None, ctypes.byref(plan)) == want
+    assert not plan.value

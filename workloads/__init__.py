@@ -25,5 +25,6 @@ from .problems import (  # noqa: F401
     batch_members,
     noise_problem,
     complex_noise_problem,
+    config5_absorbing,
     K_ABSORB,
 )

@@ -223,6 +223,28 @@ def config5(n=1023, nrhs=4, device="cpu", planes=None):
     return _noise_rhs(p, [105000 + r for r in range(nrhs)], "uniform", device=device)
 
 
+K_CONFIG5_ABSORB = KProfile(lambda z: 80.0 * (1.0 + 0.05j) * np.exp(-z),
+                            lambda z: -80.0 * (1.0 + 0.05j) * np.exp(-z),
+                            lambda z: 80.0 * (1.0 + 0.05j) * np.exp(-z), "80(1+0.05i) exp(-z)")
+
+
+def config5_absorbing(n=1023, nrhs=2, device="cpu"):
+    """The 1023^3 workload in an absorbing medium: k = 80 (1 + 0.05 i) exp(-z); complex
+    right-hand sides f_r = f*(u*) + U[-1, 1] noise + i U[-1, 1] noise (seeds 105100 + r,
+    105200 + r)."""
+    p = manufactured_sin3(n, n, n, "helm6", K_CONFIG5_ABSORB, device=device)
+    p.name = f"helm6_kexp_absorbing_{n}_x{nrhs}"
+    base = p.f[0]
+    p.u_exact = None
+    shape = tuple(base.shape)
+    out = torch.empty((nrhs,) + shape, dtype=torch.complex128, device=device)
+    for r in range(nrhs):
+        out[r] = base + torch.complex(uniform_pm1(105100 + r, shape, device=device),
+                                      uniform_pm1(105200 + r, shape, device=device))
+    p.f = out
+    return p
+
+
 def noise_problem(nx, ny, nz, scheme, seed, device="cpu", box=None, gamma=-7.5,
                   prof=None, boundary=True, nrhs=1):
     """Random RHS and z-face data on a (possibly non-cubic) grid; variable k(z)."""
