@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
     const ProbDev& p = b.P[b.perm[k]];
     const int t = item - b.start[k];
     const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRY - 1) / kRY;
-    rhs_block(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win);
+    rhs_block<true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win);
   }
 }
 

@@ -614,7 +614,18 @@ static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStr
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreads), 0, s, pd);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  // face corrections: x and y faces (6th order), z faces (6th order and the lift)
+  const bool h6 = p->d.scheme == CS3D_HELM6;
+  const int nx = p->d.nx, ny = p->d.ny, nz = p->d.nz;
+  for (int axis = 0; axis < 3 && e == hipSuccess; ++axis) {
+    if (axis < 2 && !h6) continue;
+    if (axis == 2 && !h6 && !pd.glo && !pd.ghi) continue;
+    const int npts = axis == 0 ? ny * nz : (axis == 1 ? nx * nz : nx * ny);
+    hipLaunchKernelGGL(k_rhs_faces, dim3((npts + 255) / 256, 2, nrhs), dim3(256), 0, s, pd, axis);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, const double* ghi,

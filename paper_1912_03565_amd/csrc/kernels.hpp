@@ -179,11 +179,41 @@ __device__ __forceinline__ double plane9(const double* __restrict__ w, const dou
          w[2] * (c[-sy] + c[sy]) + w[3] * c[0];
 }
 
+// Correction of F at a point (i, j, l) on the faces of the interior box normal to `axis`
+// (0: x, 1: y, 2: z): for the 6th-order operator the one-sided fourth difference along the
+// axis in place of the zero-padded central one the RHS pass formed; on the z faces also
+// minus the lift of the z-face data (both faces when nz = 1).  No contraction here: the
+// per-axis face passes and the batch's inline loop then add the same value bit for bit,
+// whatever the caller's context lets the compiler fuse.
+__device__ __forceinline__ double face_corr(const ProbDev& p, int r, int i, int j, int l, int axis) {
+#pragma clang fp contract(off)
+  const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
+  const double hz2 = p.hz * p.hz;
+  double F = 0.0;
+  if (p.scheme == kHelm6) {
+    const double* c = p.f + r * p.f_stride + i + sy * j + sz * l;
+    const long long st = axis == 0 ? 1 : (axis == 1 ? sy : sz);
+    const int n = axis == 0 ? p.nx : (axis == 1 ? p.ny : p.nz);
+    const int at = axis == 0 ? i : (axis == 1 ? j : l);
+    const bool low = at == 1, hi = at == n;
+    // the central difference as the RHS pass formed it (values beyond the grid are zero)
+    const double pad = (low ? 0.0 : c[-2 * st]) + (hi ? 0.0 : c[2 * st]) - 4.0 * (c[-st] + c[st]) + 6.0 * c[0];
+    F = -hz2 * (d4_onesided(c, st, low) - pad) * (1.0 / 240.0);
+  }
+  if (axis == 2) {
+    if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
+    if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
+  }
+  return F;
+}
+
 constexpr int kRThreads = 256;
 constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread (4)
 constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
-// one 64 x 16 tile (bx, by) over the z-chunk zc of right-hand side r
+// one 64 x 16 tile (bx, by) over the z-chunk zc of right-hand side r.  FACES: add the
+// corrections of the points on the faces of the box here (else k_rhs_faces does it)
+template <bool FACES>
 __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int zc, int r,
                                           double (*win)[kSY * kSX]) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -310,36 +340,25 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
       }
       p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] = F;
     }
-    // Points on a face of the interior box: the one-sided fourth differences of the
-    // 6th-order operator in place of the zero-padded central ones, and the lift of the
-    // z-face data, added to what was stored (a rolled loop, so the rarely taken global
-    // reads cost no registers in the code above)
-    const bool h6 = p.scheme == kHelm6;
-    const bool zface = l == 1 || l == p.nz;
-    const bool lift = (l == 1 && p.glo) || (l == p.nz && p.ghi);
-    const int jb = y0 + ty * kRRows;
-    const bool yface = jb == 1 || (jb <= p.ny && p.ny <= jb + kRRows - 1);
-    if (i <= p.nx && ((h6 && (zface || yface || i == 1 || i == p.nx)) || lift)) {
+    // FACES: the face corrections (face_corr), added axis by axis in the order of the
+    // per-axis face passes, so both ways give the same result bit for bit (a rolled loop:
+    // the rarely taken global reads cost no registers in the code above)
+    if constexpr (FACES) {
+      const bool h6 = p.scheme == kHelm6;
+      const bool zface = l == 1 || l == p.nz;
+      const bool lift = (l == 1 && p.glo) || (l == p.nz && p.ghi);
+      const int jb = y0 + ty * kRRows;
+      const bool yface = jb == 1 || (jb <= p.ny && p.ny <= jb + kRRows - 1);
+      if (i <= p.nx && ((h6 && (zface || yface || i == 1 || i == p.nx)) || lift)) {
 #pragma unroll 1
-      for (int k = 0; k < kRRows; ++k) {
-        const int j = jb + k;
-        if (j > p.ny) break;
-        const double* c = f + i + sy * j + sz * l;
-        double d4 = 0.0, F = 0.0;
-        if (h6) {
-          // central fourth difference as formed above (values beyond the grid are zero)
-          auto padded = [&](long long st, bool low, bool high) {
-            const double m2 = low ? 0.0 : c[-2 * st], p2 = high ? 0.0 : c[2 * st];
-            return m2 + p2 - 4.0 * (c[-st] + c[st]) + 6.0 * c[0];
-          };
-          if (i == 1 || i == p.nx) d4 += d4_onesided(c, 1, i == 1) - padded(1, i == 1, i == p.nx);
-          if (j == 1 || j == p.ny) d4 += d4_onesided(c, sy, j == 1) - padded(sy, j == 1, j == p.ny);
-          if (zface) d4 += d4_onesided(c, sz, l == 1) - padded(sz, l == 1, l == p.nz);
-          F = -hz2 * d4 * (1.0 / 240.0);
+        for (int k = 0; k < kRRows; ++k) {
+          const int j = jb + k;
+          if (j > p.ny) break;
+          double* u = p.u + r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+          if (h6 && (i == 1 || i == p.nx)) *u += face_corr(p, r, i, j, l, 0);
+          if (h6 && (j == 1 || j == p.ny)) *u += face_corr(p, r, i, j, l, 1);
+          if ((h6 && zface) || lift) *u += face_corr(p, r, i, j, l, 2);
         }
-        if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
-        if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
-        if (F != 0.0) p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] += F;
       }
     }
   };
@@ -377,13 +396,44 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
   }
 }
 
-// grid: (x tiles) x (y tiles) x (z chunks x right-hand sides), taken in XCD order
+// grid: (x tiles) x (y tiles) x (z chunks x right-hand sides), taken in XCD order; the
+// face corrections follow in k_rhs_faces
 __global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
   __shared__ double win[kRSlots][kSY * kSX];
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
-  rhs_block(p, bx, by, bz % nzc, bz / nzc, win);
+  rhs_block<false>(p, bx, by, bz % nzc, bz / nzc, win);
+}
+
+// Corrections of F on one pair of faces of the interior box (axis 0: x, 1: y, 2: z), one
+// point per thread: for the 6th-order operator the one-sided fourth difference along the
+// axis in place of the zero-padded central one k_rhs formed; on the z faces also minus the
+// lift of the z-face data.  One launch per axis, so no point is updated twice at once.
+// grid: (ceil(face points / 256), 2 faces, right-hand sides)
+__global__ void __launch_bounds__(256) k_rhs_faces(ProbDev p, int axis) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int high = blockIdx.y, r = blockIdx.z;
+  int i, j, l;
+  if (axis == 0) {
+    if (e >= p.ny * p.nz) return;
+    j = 1 + e % p.ny;
+    l = 1 + e / p.ny;
+    i = high ? p.nx : 1;
+  } else if (axis == 1) {
+    if (e >= p.nx * p.nz) return;
+    i = 1 + e % p.nx;
+    l = 1 + e / p.nx;
+    j = high ? p.ny : 1;
+  } else {
+    if (e >= p.nx * p.ny) return;
+    i = 1 + e % p.nx;
+    j = 1 + e / p.nx;
+    l = high ? p.nz : 1;
+    if (high && p.nz == 1) return;  // a single plane: the low-face thread lifts both
+  }
+  const double F = face_corr(p, r, i, j, l, axis);
+  p.u[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1))] += F;
 }
 
 // ---------------------------------------------------------------------------
