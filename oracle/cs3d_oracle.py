@@ -39,6 +39,20 @@ listed with its justification in the design notes of the repository):
   R16 k may be complex (Section 1 allows it): the weights, the modal eigenvalues, the
       right-hand side and U are then complex; the sine transforms are real and act on
       the real and imaginary parts alike, so only the tridiagonal solves are complex.
+  R21 Neumann sides (Section 1 names the extension to Neumann conditions on the sides,
+      without a discretisation): du/dn = 0 on the x and y faces is closed by even
+      reflection.  The side nodes i = 0, N_x+1 (j = 0, N_y+1) become unknowns, every
+      node carries the scheme's own row, and a value beyond a side is the mirror image
+      about it: U_{-1} = U_1, U_{N+2} = U_N, and the same for f in the right-hand side,
+      whose x and y differences are then all central.  The reflected 9-point plane
+      blocks are diagonalised by the cosine vectors cos(pi n i/M), n, i = 0..M = N+1,
+      with the eigenvalue formula of Section 3.6 at theta_n = n pi/M, so a DCT-I takes
+      the place of the DST-I.  The scheme keeps its order for solutions whose odd
+      normal derivatives vanish on the sides (the cosine class), as the Dirichlet
+      reading keeps it when the even derivatives of f vanish there.
+
+Neumann arrays (sides="neumann"): the unknowns form arrays of shape (nz, ny+2, nx+2)
+(every x/y node of a plane); f and the z-face planes keep their closed-grid shapes.
 """
 import numpy as np
 
@@ -56,7 +70,8 @@ def _complex_of(dtype):
     return np.clongdouble if dtype == np.longdouble else np.complex128
 
 __all__ = [
-    "SCHEMES", "stencil_weights", "rhs", "lift", "sine_matrix", "dst2",
+    "SCHEMES", "stencil_weights", "rhs", "lift", "sine_matrix", "dst2", "cosine_matrix", "dct2",
+    "mirror_pad",
     "modal_eigenvalues", "thomas", "solve_modal", "solve", "apply_operator",
     "assemble_dense", "dense_solve", "error_norms", "OracleResult", "closed",
 ]
@@ -186,8 +201,19 @@ def _d2d2(f, a, b):
     return s[tuple(sl)]
 
 
-def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0):
+def mirror_pad(a, width):
+    """Extend the last two axes (y, x) of a by ``width`` mirrored layers on each side:
+    a value beyond a side is the one at the same distance inside (reading R21)."""
+    pad = [(0, 0)] * (a.ndim - 2) + [(width, width), (width, width)]
+    return np.pad(a, pad, mode="reflect")
+
+
+def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0, sides="dirichlet"):
     """F on the interior from f on the closed grid (shape (nz+2, ny+2, nx+2)).
+
+    sides="neumann" (reading R21): F on every x/y node, shape (nz, ny+2, nx+2); f is
+    mirrored about the sides by two layers and the Dirichlet formula evaluated on the
+    extended grid, whose one-sided side differences then fall outside what is kept.
 
     helm2: F = h_z^2 f (Section 3.2).
     helm4: F = h_z^2 (1 + sum_alpha h_alpha^2 delta_alpha^2/12) f (eq. scheme4, Section 3.3).
@@ -199,6 +225,8 @@ def rhs(scheme, f, hx, hy, hz, k2=None, k2_z=None, gamma=0.0):
            coefficient of f_{alpha alpha alpha alpha} is 1/360.
     """
     f = _num(f)
+    if sides == "neumann":
+        return rhs(scheme, mirror_pad(f, 2), hx, hy, hz, k2, k2_z, gamma)[:, 1:-1, 1:-1]
     nz = f.shape[0] - 2
     inner = f[1:-1, 1:-1, 1:-1]
     if scheme == "helm2":
@@ -232,26 +260,32 @@ def _plane9(w, P):
             + d * P[1:-1, 1:-1])
 
 
-def lift(W, F, g_lo=None, g_hi=None):
-    """F_1 -= (plane -1 weights of row 1) * g_lo;  F_Nz -= (plane +1 weights of row Nz) * g_hi."""
+def lift(W, F, g_lo=None, g_hi=None, sides="dirichlet"):
+    """F_1 -= (plane -1 weights of row 1) * g_lo;  F_Nz -= (plane +1 weights of row Nz) * g_hi.
+
+    Neumann sides: the planes are mirrored by one layer, so every node of a plane takes part."""
     parts = [F, W] + [g for g in (g_lo, g_hi) if g is not None]
     F = np.array(F, dtype=np.result_type(*[_num(x) for x in parts]), copy=True)
+    ext = (lambda g: mirror_pad(_num(g), 1)) if sides == "neumann" else _num
     if g_lo is not None:
-        F[0] -= _plane9(W[0, 0], _num(g_lo))
+        F[0] -= _plane9(W[0, 0], ext(g_lo))
     if g_hi is not None:
-        F[-1] -= _plane9(W[-1, 2], _num(g_hi))
+        F[-1] -= _plane9(W[-1, 2], ext(g_hi))
     return F
 
 
-def apply_operator(W, U_closed):
+def apply_operator(W, U_closed, sides="dirichlet"):
     """(A U)_{i,j,l} = sum_o sum of the in-plane 9-point weights of plane l+o (eq. stencil27).
 
-    U_closed holds the solution on the closed grid including its boundary values.
+    U_closed holds the solution on the closed grid including its boundary values (Neumann
+    sides: shape (nz+2, ny+2, nx+2), the nodes of every plane, mirrored by one layer here).
     This is the residual path: it shares nothing with the transform solve.
     """
     U = np.asarray(U_closed)
     if U.dtype not in (np.longdouble, np.clongdouble):
         U = _num(U)
+    if sides == "neumann":
+        U = mirror_pad(U, 1)
     nz = U.shape[0] - 2
     out = np.zeros((nz, U.shape[1] - 2, U.shape[2] - 2), dtype=np.result_type(U, W))
     for l in range(1, nz + 1):
@@ -291,14 +325,49 @@ def dst2(F, dtype=None):
     return np.matmul(Sy, G)         # y-sums:  Fbar[l, m, n] = sum_j Sy[m, j] G[l, j, n]
 
 
+def cosine_matrix(nodes, dtype=np.float64):
+    """DCT-I of a line of ``nodes`` = M + 1 values (reading R21):
+    C[k, i] = e_i cos(pi k i/M), k, i = 0..M, e_0 = e_M = 1/2, e_i = 1 otherwise.
+    C C = (M/2) I; the product k*i is reduced modulo 2M in integers first."""
+    M = nodes - 1
+    k = np.arange(nodes)
+    r = (np.outer(k, k) % (2 * M)).astype(dtype)
+    C = np.cos(_pi(dtype) * r / M)
+    C[:, 0] *= 0.5
+    C[:, M] *= 0.5
+    return C
+
+
+def dct2(F, dtype=None, inverse=False):
+    """Per plane: C_y F C_x^T (x sums, then y sums); inverse=True also scales by
+    (2/M_x)(2/M_y), which makes it the inverse transform."""
+    if np.iscomplexobj(F):
+        return dct2(np.real(F), dtype, inverse) + 1j * dct2(np.imag(F), dtype, inverse)
+    dtype = F.dtype if dtype is None else dtype
+    F = np.asarray(F, dtype=dtype)
+    nz, ny, nx = F.shape
+    Cx, Cy = cosine_matrix(nx, dtype), cosine_matrix(ny, dtype)
+    out = np.matmul(Cy, np.matmul(F, Cx.T))
+    if inverse:
+        out = out * (np.asarray(4, dtype=dtype) / ((nx - 1) * (ny - 1)))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Modal tridiagonal systems, Section 3.6.
 # ----------------------------------------------------------------------------
-def modal_eigenvalues(W, nx, ny, dtype=np.float64):
-    """lam[l-1, o+1, m-1, n-1] = 4a cos(th_n) cos(ph_m) + 2b cos(th_n) + 2c cos(ph_m) + d."""
+def modal_eigenvalues(W, nx, ny, dtype=np.float64, sides="dirichlet"):
+    """lam[l-1, o+1, m-1, n-1] = 4a cos(th_n) cos(ph_m) + 2b cos(th_n) + 2c cos(ph_m) + d.
+
+    Dirichlet: th_n = n pi/(nx+1), n = 1..nx.  Neumann (nx, ny = nodes per line, R21):
+    th_n = n pi/(nx-1), n = 0..nx-1."""
     pi = _pi(dtype)
-    ct = np.cos(pi * np.arange(1, nx + 1, dtype=dtype) / (nx + 1))[None, :]
-    cp = np.cos(pi * np.arange(1, ny + 1, dtype=dtype) / (ny + 1))[:, None]
+    if sides == "neumann":
+        ct = np.cos(pi * np.arange(nx, dtype=dtype) / (nx - 1))[None, :]
+        cp = np.cos(pi * np.arange(ny, dtype=dtype) / (ny - 1))[:, None]
+    else:
+        ct = np.cos(pi * np.arange(1, nx + 1, dtype=dtype) / (nx + 1))[None, :]
+        cp = np.cos(pi * np.arange(1, ny + 1, dtype=dtype) / (ny + 1))[:, None]
     W = np.asarray(W, dtype=_complex_of(dtype) if np.iscomplexobj(W) else dtype)
     a, b, c, d = (W[..., q][:, :, None, None] for q in range(4))
     return 4.0 * a * cp * ct + 2.0 * b * ct + 2.0 * c * cp + d
@@ -335,10 +404,10 @@ def thomas(lam, Fbar):
     return Wm, minpiv, bad
 
 
-def solve_modal(W, Fbar):
+def solve_modal(W, Fbar, sides="dirichlet"):
     nz, ny, nx = Fbar.shape
     real = np.real(Fbar[:1, :1, :1]).dtype
-    lam = modal_eigenvalues(W, nx, ny, real)
+    lam = modal_eigenvalues(W, nx, ny, real, sides)
     if np.iscomplexobj(lam) and not np.iscomplexobj(Fbar):
         Fbar = Fbar.astype(_complex_of(real))
     return thomas(lam, Fbar)
@@ -350,7 +419,7 @@ class OracleResult:
 
 
 def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
-          g_lo=None, g_hi=None, W=None, F=None, dtype=np.float64):
+          g_lo=None, g_hi=None, W=None, F=None, dtype=np.float64, sides="dirichlet"):
     """U = A^{-1}(F - lift): weights -> F -> lift -> DST -> Thomas -> inverse DST (Section 3.6).
 
     Either f (closed grid) with a scheme, or an assembled interior F with explicit W.
@@ -359,16 +428,23 @@ def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
     dtype=np.longdouble (x87 extended, 64-bit significand) the oracle's own rounding
     stays far below the FP64 level even where small pivots amplify it, so the result is
     the FP64 system's solution to about 1e-16.  U is returned in FP64.
+
+    sides="neumann" (reading R21): U on every node of each plane, the DCT-I in place of
+    the DST-I.
     """
     if W is None:
         nz = np.asarray(f).shape[0] - 2
         W = stencil_weights(scheme, nz, hx, hy, hz, k2, k2_z, k2_zz, gamma)
     if F is None:
-        F = rhs(scheme, f, hx, hy, hz, k2, k2_z, gamma)
-    Fl = lift(W, F, g_lo, g_hi)
-    Fbar = dst2(Fl, dtype)
-    What, minpiv, bad = solve_modal(W, Fbar)
-    U = dst2(What)    # V is its own inverse
+        F = rhs(scheme, f, hx, hy, hz, k2, k2_z, gamma, sides)
+    Fl = lift(W, F, g_lo, g_hi, sides)
+    if sides == "neumann":
+        What, minpiv, bad = solve_modal(W, dct2(Fl, dtype), sides)
+        U = dct2(What, inverse=True)
+    else:
+        Fbar = dst2(Fl, dtype)
+        What, minpiv, bad = solve_modal(W, Fbar)
+        U = dst2(What)    # V is its own inverse
     U = U.astype(np.complex128 if np.iscomplexobj(U) else np.float64)
     return OracleResult(U, W, F, minpiv, bad)
 
@@ -377,7 +453,10 @@ def solve(scheme, f, hx, hy, hz, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
 # Brute force for tiny grids: the assembled 27-diagonal matrix (eq. stencil27)
 # and a dense partial-pivot LU solve.
 # ----------------------------------------------------------------------------
-def assemble_dense(W, nx, ny, nz):
+def assemble_dense(W, nx, ny, nz, sides="dirichlet"):
+    """The 27-diagonal matrix row by row (eq. stencil27).  Neumann sides (nx, ny = nodes
+    per line, R21): a neighbour beyond a side is its mirror image, whose entry takes the
+    weight (the two neighbours of a side node then add up on one column)."""
     n = nx * ny * nz
     A = np.zeros((n, n), dtype=np.result_type(W, np.float64))
     for l in range(nz):
@@ -392,6 +471,9 @@ def assemble_dense(W, nx, ny, nz):
                     for di in (-1, 0, 1):
                         for dj in (-1, 0, 1):
                             ii, jj = i + di, j + dj
+                            if sides == "neumann":
+                                ii = -ii if ii < 0 else (2 * (nx - 1) - ii if ii >= nx else ii)
+                                jj = -jj if jj < 0 else (2 * (ny - 1) - jj if jj >= ny else jj)
                             if not (0 <= ii < nx and 0 <= jj < ny):
                                 continue
                             w = (a if (di and dj) else b if di else c if dj else d)
@@ -399,19 +481,24 @@ def assemble_dense(W, nx, ny, nz):
     return A
 
 
-def dense_solve(W, Fl):
+def dense_solve(W, Fl, sides="dirichlet"):
     nz, ny, nx = Fl.shape
-    A = assemble_dense(W, nx, ny, nz)
+    A = assemble_dense(W, nx, ny, nz, sides)
     return np.linalg.solve(A, Fl.reshape(-1)).reshape(nz, ny, nx)
 
 
 # ----------------------------------------------------------------------------
 # Error measures, Section 5.1 (with reading R12 for the two L2 normalisations).
 # ----------------------------------------------------------------------------
-def closed(U, g_lo=None, g_hi=None):
+def closed(U, g_lo=None, g_hi=None, sides="dirichlet"):
+    """U with its z-face planes (and, for Dirichlet sides, the zero x/y ring)."""
     nz, ny, nx = U.shape
-    C = np.zeros((nz + 2, ny + 2, nx + 2), dtype=U.dtype)
-    C[1:-1, 1:-1, 1:-1] = U
+    if sides == "neumann":
+        C = np.zeros((nz + 2, ny, nx), dtype=U.dtype)
+        C[1:-1] = U
+    else:
+        C = np.zeros((nz + 2, ny + 2, nx + 2), dtype=U.dtype)
+        C[1:-1, 1:-1, 1:-1] = U
     if g_lo is not None:
         C[0] = g_lo
     if g_hi is not None:
@@ -419,7 +506,7 @@ def closed(U, g_lo=None, g_hi=None):
     return C
 
 
-def error_norms(U, u_exact_interior, W=None, F=None, g_lo=None, g_hi=None):
+def error_norms(U, u_exact_interior, W=None, F=None, g_lo=None, g_hi=None, sides="dirichlet"):
     e = u_exact_interior - U
     out = {
         "max_err": float(np.max(np.abs(e))),
@@ -427,7 +514,7 @@ def error_norms(U, u_exact_interior, W=None, F=None, g_lo=None, g_hi=None):
         "l2_err_u": float(np.linalg.norm(e) / np.linalg.norm(u_exact_interior)),
     }
     if W is not None and F is not None:
-        r = F - apply_operator(W, closed(U, g_lo, g_hi))
+        r = F - apply_operator(W, closed(U, g_lo, g_hi, sides), sides)
         out["l2_res"] = float(np.linalg.norm(r))
-        out["rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(lift(W, F, g_lo, g_hi)))
+        out["rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(lift(W, F, g_lo, g_hi, sides)))
     return out

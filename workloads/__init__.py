@@ -25,6 +25,8 @@ from .problems import (  # noqa: F401
     batch_members,
     noise_problem,
     complex_noise_problem,
+    manufactured_cos2,
+    neumann_noise_problem,
     config5_absorbing,
     K_ABSORB,
 )

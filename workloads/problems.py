@@ -67,6 +67,9 @@ class Problem:
     gamma: float = 0.0
     u_exact: Optional[torch.Tensor] = None  # [nrhs, nz+2, ny+2, nx+2] or None
     meta: dict = field(default_factory=dict)
+    # "dirichlet": u = 0 on the x/y faces; "neumann": du/dn = 0 there, and every x/y node of
+    # the closed grid is an unknown
+    sides: str = "dirichlet"
 
     @property
     def nrhs(self):
@@ -74,6 +77,8 @@ class Problem:
 
     @property
     def unknowns(self):
+        if self.sides == "neumann":
+            return (self.nx + 2) * (self.ny + 2) * self.nz
         return self.nx * self.ny * self.nz
 
 
@@ -158,6 +163,42 @@ def manufactured_sin3(nx, ny, nz, scheme, prof, device="cpu", box=None, planes=N
     f = _outer3((k2t + lap) * sz, sy, sx)
     return Problem(f"sin3_{scheme}_{nx}x{ny}x{nz}", scheme, nx, ny, nz, hx, hy, hz,
                    f=f[None], k2=k2, k2_z=k2z, k2_zz=k2zz, u_exact=u[None])
+
+
+def manufactured_cos2(nx, ny, nz, scheme, prof, device="cpu", box=None):
+    """Neumann sides: u = cos(pi x/Lx) cos(2 pi y/Ly) (sin(3 pi z/Lz) + cos(pi z/Lz)/2).
+
+    du/dn = 0 on the x and y faces (every odd x/y derivative vanishes there) and non-zero
+    Dirichlet data u(x, y, 0), u(x, y, Lz) on the z faces."""
+    if box is None:
+        box = (1.0, 1.0, 1.0)
+    hx, hy, hz = box[0] / (nx + 1), box[1] / (ny + 1), box[2] / (nz + 1)
+    x, y, z = _axis(nx, hx, device=device), _axis(ny, hy, device=device), _axis(nz, hz, device=device)
+    cx = torch.cos(math.pi * x / box[0])
+    cy = torch.cos(2 * math.pi * y / box[1])
+    a, b = 3 * math.pi / box[2], math.pi / box[2]
+    gz = torch.sin(a * z) + 0.5 * torch.cos(b * z)
+    gzz = -a * a * torch.sin(a * z) - 0.5 * b * b * torch.cos(b * z)
+    lapxy = -math.pi ** 2 * (1.0 / box[0] ** 2 + 4.0 / box[1] ** 2)
+    k2, k2z, k2zz = _zsamples(nz, hz, prof)
+    k2t = torch.as_tensor(k2, device=device)
+    u = _outer3(gz, cy, cx)
+    f = _outer3((k2t + lapxy) * gz + gzz, cy, cx)
+    return Problem(f"cos2_{scheme}_{nx}x{ny}x{nz}", scheme, nx, ny, nz, hx, hy, hz,
+                   f=f[None], g_lo=u[None, 0].clone(), g_hi=u[None, -1].clone(), k2=k2, k2_z=k2z,
+                   k2_zz=k2zz, u_exact=u[None], sides="neumann")
+
+
+def neumann_noise_problem(nx, ny, nz, scheme, seed, device="cpu", nrhs=1, boundary=True):
+    """Neumann sides, random f on every node of the closed grid and random z-face planes
+    (all nodes); k(z) = 6 + 2 sin 3z; the grids of ``noise_problem``."""
+    p = noise_problem(nx, ny, nz, scheme, seed, device=device, boundary=False, nrhs=nrhs)
+    if boundary:
+        p.g_lo = uniform_pm1(seed + 1, (nrhs, ny + 2, nx + 2), device=device)
+        p.g_hi = uniform_pm1(seed + 2, (nrhs, ny + 2, nx + 2), device=device)
+    p.sides = "neumann"
+    p.name = f"neu_{scheme}_{nx}x{ny}x{nz}_s{seed}"
+    return p
 
 
 def _zero_ring_(f):
