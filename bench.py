@@ -244,6 +244,51 @@ def complex_bench(cs3d, dev, n, nrhs, steps, warmup):
     return out
 
 
+def neumann_bench(cs3d, dev, n, nrhs, steps, warmup):
+    """The 6th-order workload with Neumann sides (du/dn = 0 on the x and y faces, DCT-I
+    transforms): k = 80 exp(-z), n^3 interior grid whose (n+2)^2 n nodes are all unknown,
+    f_r = f*(cos pi x cos 2pi y (sin 3pi z + cos(pi z)/2)) + U[-1, 1] noise (seeds 106000 + r),
+    z-face data of u*.  n = 511 is the largest grid on the cosine FFT path."""
+    import torch
+
+    import workloads as WL
+
+    p = WL.manufactured_cos2(n, n, n, "helm6", WL.problems.K_CONFIG5, device=dev)
+    base = p.f[0]
+    f = torch.empty((nrhs,) + tuple(base.shape), dtype=torch.float64, device=dev)
+    for r in range(nrhs):
+        torch.add(WL.uniform_pm1(106000 + r, tuple(base.shape), device=dev), base, out=f[r])
+    gl = p.g_lo.expand(nrhs, -1, -1).contiguous()
+    gh = p.g_hi.expand(nrhs, -1, -1).contiguous()
+    del p.f, base
+    plan = cs3d.plan_for_problem(p, max_rhs=nrhs, device=dev)
+    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        plan.solve(f, gl, gh, out=u)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(f, gl, gh, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = plan.stats()
+    nodes = nrhs * (n + 2) ** 2 * n
+    out = {"workload": f"helm6_kexp_neumann_sides_{n}^3_x{nrhs}rhs", "unknowns": nodes,
+           "ms_per_step": round(ms, 4), "value": round(nodes / (ms / 1e3), 1), "unit": "unknowns/s",
+           "stage_ms": [round(x, 4) for x in st["stage_ms"]], "min_abs_pivot": st["min_abs_pivot"],
+           "bad_pivots": st["bad_pivots"]}
+    log(f"[bench] neumann sides: {ms:.3f} ms per step of {nrhs} x {(n + 2) ** 2 * n} unknowns; "
+        f"stages {out['stage_ms']}")
+    plan.close()
+    del plan, u, f, gl, gh
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +301,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
     ap.add_argument("--no-complex", action="store_true", help="skip the absorbing-medium (complex k) timing")
+    ap.add_argument("--no-neumann", action="store_true", help="skip the Neumann-sides timing")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune each plan before timing (the defaults are the tuned shapes of this workload)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -333,11 +379,14 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_bench(cs3d, dev, args.steps, args.warmup)
+    del p  # the main workload's fields
+    torch.cuda.empty_cache()
     cplx = None
     if not args.no_complex:
-        del p
-        torch.cuda.empty_cache()
         cplx = complex_bench(cs3d, dev, n, max(1, nrhs // 2), args.steps, args.warmup)
+    neu = None
+    if not args.no_neumann:
+        neu = neumann_bench(cs3d, dev, min(n, 511), nrhs, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -362,6 +411,7 @@ def main():
         "fp64_path_algorithmic_GBs": round(whole_gbs, 1),
         "batch": batch,
         "complex_k": cplx,
+        "neumann_sides": neu,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -17,7 +17,9 @@
  * the convection-diffusion equation u_xx + u_yy + u_zz + gamma u_z = f
  * (Section 3.5), on a box with N_alpha interior points and
  * h_alpha = L_alpha/(N_alpha+1) (Section 2); u = 0 on the x and y faces and
- * Dirichlet data g on the two z faces.
+ * Dirichlet data g on the two z faces.  With desc.sides = CS3D_SIDES_NEUMANN the x and
+ * y faces carry du/dn = 0 instead (the extension Section 1 mentions): the side nodes
+ * are unknowns too, closed by even reflection, and a DCT-I replaces the DST-I.
  *
  * Conventions shared by every entry point:
  *  - Layout: x fastest.  Interior arrays hold nx*ny*nz doubles with point
@@ -25,6 +27,10 @@
  *    Closed-grid arrays hold (nx+2)*(ny+2)*(nz+2) doubles with point (i, j, l)
  *    (0-based, boundary included) at i + (nx+2)*(j + (ny+2)*l).  z-face data are
  *    closed planes of (nx+2)*(ny+2) doubles, ring included.
+ *  - Neumann sides: the x and y side nodes are unknowns, so "interior" arrays hold
+ *    (nx+2)*(ny+2)*nz doubles with node (i, j, l) (i, j 0-based, l 1-based) at
+ *    i + (nx+2)*(j + (ny+2)*(l-1)); closed-grid arrays and z-face planes keep their
+ *    shapes (every x/y node of the closed grid is then a point of the system).
  *  - Several right-hand sides are stored back to back (stride = one array).
  *  - Complex plans (desc.k2_im != NULL): nrhs counts complex right-hand sides and every
  *    complex array is planar, the real part followed by the imaginary part, each of the
@@ -77,6 +83,19 @@ typedef enum {
                            solves, FP64 27-point residual and refinement */
 } cs3d_precision;
 
+/* Conditions on the x and y faces. */
+enum {
+  CS3D_SIDES_DIRICHLET = 0, /* u = 0 (Section 1, eq. bc); DST-I in x and y */
+  CS3D_SIDES_NEUMANN = 1    /* du/dn = 0: the scheme's rows also on the side nodes, the
+                               values beyond a side mirrored about it (u_{-1} = u_1,
+                               likewise f); DCT-I in x and y.  Full order for solutions
+                               whose odd normal derivatives vanish on the sides (the
+                               cosine class), as the Dirichlet path's order asks the even
+                               derivatives of f to vanish there.  FP64, real k, plans only;
+                               nx + 2 and ny + 2 at most 1023 (FFT path where nx + 1 is a
+                               power of two in 64..512, direct cosine sums otherwise) */
+};
+
 typedef struct {
   int nx, ny, nz;          /* interior points per axis (Section 2); >= 1.  The FFT line
                               transform serves N+1 in {64,...,1024} (powers of two), a
@@ -100,6 +119,10 @@ typedef struct {
                               CS3D_FP64 only (else E_UNSUPPORTED). */
   const double* k2_z_im;   /* host, nz+2 samples of Im (k^2)_z; complex HELM6 only */
   const double* k2_zz_im;  /* host, nz+2 samples of Im (k^2)_zz; complex HELM6 only */
+  int sides;               /* CS3D_SIDES_DIRICHLET (0, the default of a zeroed desc) or
+                              CS3D_SIDES_NEUMANN; Neumann with mixed precision, complex k or
+                              a batch gives E_UNSUPPORTED, with nx + 2 or ny + 2 > 1023
+                              E_INVAL */
 } cs3d_desc;
 
 typedef struct {

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cs3d.h"
@@ -91,6 +92,9 @@ struct cs3d_plan_s {
   double* dLCi = nullptr;
   double* dk2i = nullptr;
   double* dk2zi = nullptr;
+  // Neumann sides: d.nx, d.ny count the nodes of a plane (interior + 2 side nodes) and
+  // the line transforms are DCT-I
+  bool neu = false;
 };
 
 // ---------------------------------------------------------------------------
@@ -213,6 +217,23 @@ static void sines(int M, std::vector<double>& s) {
     s[k] = (double)sinl(3.14159265358979323846264338327950288L * (long double)k / (long double)M);
 }
 
+// cos(pi k/M), k < 2M: the direct sums of the cosine transform
+static void cosines(int M, std::vector<double>& c) {
+  c.resize(2 * (size_t)M);
+  for (int k = 0; k < 2 * M; ++k)
+    c[k] = (double)cosl(3.14159265358979323846264338327950288L * (long double)k / (long double)M);
+}
+
+// Neumann sides: s_k = 1 - cos(pi k/M) = 2 sin^2(pi k/(2M)) for the modes k = 0..M of a
+// line of M + 1 nodes (entry k = position k + 1 - 1)
+static void one_minus_cosines_dct(int M, std::vector<double>& c) {
+  c.resize((size_t)M + 1);
+  for (int k = 0; k <= M; ++k) {
+    const long double sn = sinl(3.14159265358979323846264338327950288L * (long double)k / (2.0L * M));
+    c[k] = (double)(2.0L * sn * sn);
+  }
+}
+
 // s_k = 1 - cos(pi k/(n+1)) = 2 sin^2(pi k/(2(n+1))), k = 1..n, without cancellation
 static void one_minus_cosines(int n, std::vector<double>& c) {
   c.resize(n);
@@ -286,6 +307,12 @@ static cs3d_status validate(const cs3d_desc* d) {
     default:
       return CS3D_E_INVAL;
   }
+  if (d->sides != CS3D_SIDES_DIRICHLET && d->sides != CS3D_SIDES_NEUMANN) return CS3D_E_INVAL;
+  if (d->sides == CS3D_SIDES_NEUMANN) {
+    // lines of nx + 2 (ny + 2) nodes within the 1023-value line layout of the passes
+    if (d->nx + 2 > kMaxN || d->ny + 2 > kMaxN) return CS3D_E_INVAL;
+    if (d->precision != CS3D_FP64 || d->k2_im) return CS3D_E_UNSUPPORTED;
+  }
   if (d->k2_im) {  // complex k: Helmholtz schemes, FP64
     if (d->scheme == CS3D_HELM6 && (!d->k2_z_im || !d->k2_zz_im)) return CS3D_E_INVAL;
     if (d->scheme != CS3D_HELM2 && d->scheme != CS3D_HELM4 && d->scheme != CS3D_HELM6) return CS3D_E_UNSUPPORTED;
@@ -327,11 +354,17 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   p->d.k2 = p->d.k2_z = p->d.k2_zz = p->d.weights = nullptr;  // host arrays are not kept
   p->d.k2_im = p->d.k2_z_im = p->d.k2_zz_im = nullptr;
   p->cplx = desc->k2_im != nullptr;
+  p->neu = desc->sides == CS3D_SIDES_NEUMANN;
+  // both kinds: the transform of a line spans M = N_interior + 1 intervals
   p->Mx = desc->nx + 1;
   p->My = desc->ny + 1;
   p->fx = fft_len(desc->nx);
   p->fy = fft_len(desc->ny);
-  p->ldy = ((desc->ny + 1 + 15) / 16) * 16;
+  if (p->neu) {
+    p->d.nx = desc->nx + 2;  // the side nodes are unknowns
+    p->d.ny = desc->ny + 2;
+  }
+  p->ldy = ((p->d.ny + 1 + 15) / 16) * 16;
   p->tune.ywpl = (p->fy == 1024) ? 2 : 1;
   // long z-columns: fewer halo planes per workgroup; FP32 transforms leave registers for
   // two right-hand sides per y-pass workgroup (the autotuner's choices at 1023^3)
@@ -358,14 +391,24 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
       for (int i = 0; i < nzp; ++i) k2zi[i] = desc->k2_z_im[i];
   }
   std::vector<double2> twx, twy;
-  one_minus_cosines(desc->nx, ctx);
-  one_minus_cosines(desc->ny, cty);
+  if (p->neu) {
+    one_minus_cosines_dct(p->Mx, ctx);
+    one_minus_cosines_dct(p->My, cty);
+  } else {
+    one_minus_cosines(desc->nx, ctx);
+    one_minus_cosines(desc->ny, cty);
+  }
   if (p->cplx) modal_coefficients_c(p->hW, hWi, lc, lci);
   else modal_coefficients(p->hW, lc);
   twiddles(p->Mx, twx);
   twiddles(p->My, twy);
-  sines(p->Mx, sx);
-  sines(p->My, sy);
+  if (p->neu) {
+    cosines(p->Mx, sx);
+    cosines(p->My, sy);
+  } else {
+    sines(p->Mx, sx);
+    sines(p->My, sy);
+  }
   CS3D_TRY(dalloc(&p->dW, p->hW.size()));
   CS3D_TRY(dalloc(&p->dLC, lc.size()));
   CS3D_TRY(dalloc(&p->dk2, k2.size()));
@@ -495,26 +538,26 @@ static int resident_blocks(KernelT kern, int threads, size_t lds, int ntiles) {
   return (int)(b < ntiles ? b : ntiles);
 }
 
-template <typename T, int MX>
+template <typename T, int MX, int KIND = kDst>
 static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX, KIND>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX>, 64 * kTileJ, lds, ntiles) : ntiles;
-  return launch(k_fwd_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX, KIND>, 64 * kTileJ, lds, ntiles) : ntiles;
+  return launch(k_fwd_x<T, MX, KIND>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
-template <typename T, int MX>
+template <typename T, int MX, int KIND = kDst>
 static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX, KIND>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = p->tune.xpersist ? resident_blocks(k_inv_x<T, MX>, 64 * kTileJ, lds, ntiles) : ntiles;
-  return launch(k_inv_x<T, MX>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_inv_x<T, MX, KIND>, 64 * kTileJ, lds, ntiles) : ntiles;
+  return launch(k_inv_x<T, MX, KIND>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
 // grid: (line groups, groups of NR right-hand sides)
@@ -526,16 +569,16 @@ static dim3 y_grid(const cs3d_plan p, int nrhs) {
 
 // right-hand sides per y-pass workgroup: the tuned choice (1, 2 or 4), at most what the
 // register budget of the transform size allows
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 static hipError_t run_y_fwd_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  return launch(k_fwd_y<T, MY, WPL, NR>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY), lds_bytes_y_t<T, MY, WPL>(p),
-                s, pd, nrhs);
+  return launch(k_fwd_y<T, MY, WPL, NR, KIND>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
+                lds_bytes_y_t<T, MY, WPL>(p), s, pd, nrhs);
 }
 
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 static hipError_t run_y_back_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  return launch(k_back_y<T, MY, WPL, NR>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY), lds_bytes_y_t<T, MY, WPL>(p),
-                s, pd, nrhs);
+  return launch(k_back_y<T, MY, WPL, NR, KIND>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
+                lds_bytes_y_t<T, MY, WPL>(p), s, pd, nrhs);
 }
 
 static int y_rhs(const cs3d_plan p, int nrhs, int nrmax) {
@@ -544,41 +587,41 @@ static int y_rhs(const cs3d_plan p, int nrhs, int nrmax) {
   return nr;
 }
 
-template <typename T, int MY, int WPL>
+template <typename T, int MY, int WPL, int KIND = kDst>
 static hipError_t run_y_fwd_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  if constexpr (YCfg<MY, WPL>::NRMAX >= 4) {
+  if constexpr (YCfg<MY, WPL, KIND>::NRMAX >= 4) {
     const int nr = y_rhs(p, nrhs, 4);
-    if (nr == 4) return run_y_fwd_n<T, MY, WPL, 4>(p, pd, nrhs, s);
-    if (nr == 2) return run_y_fwd_n<T, MY, WPL, 2>(p, pd, nrhs, s);
+    if (nr == 4) return run_y_fwd_n<T, MY, WPL, 4, KIND>(p, pd, nrhs, s);
+    if (nr == 2) return run_y_fwd_n<T, MY, WPL, 2, KIND>(p, pd, nrhs, s);
   }
-  return run_y_fwd_n<T, MY, WPL, 1>(p, pd, nrhs, s);
+  return run_y_fwd_n<T, MY, WPL, 1, KIND>(p, pd, nrhs, s);
 }
 
-template <typename T, int MY, int WPL>
+template <typename T, int MY, int WPL, int KIND = kDst>
 static hipError_t run_y_back_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  if constexpr (YCfg<MY, WPL>::NRMAX >= 4) {
+  if constexpr (YCfg<MY, WPL, KIND>::NRMAX >= 4) {
     const int nr = y_rhs(p, nrhs, 4);
-    if (nr == 4) return run_y_back_n<T, MY, WPL, 4>(p, pd, nrhs, s);
-    if (nr == 2) return run_y_back_n<T, MY, WPL, 2>(p, pd, nrhs, s);
+    if (nr == 4) return run_y_back_n<T, MY, WPL, 4, KIND>(p, pd, nrhs, s);
+    if (nr == 2) return run_y_back_n<T, MY, WPL, 2, KIND>(p, pd, nrhs, s);
   }
-  return run_y_back_n<T, MY, WPL, 1>(p, pd, nrhs, s);
+  return run_y_back_n<T, MY, WPL, 1, KIND>(p, pd, nrhs, s);
 }
 
 // waves per y-line: the tuned choice where two are possible (M >= 512), else one
-template <typename T, int MY>
+template <typename T, int MY, int KIND = kDst>
 static hipError_t run_y_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   if constexpr (MY >= 512) {
-    if (p->tune.ywpl == 2) return run_y_fwd_w<T, MY, 2>(p, pd, nrhs, s);
+    if (p->tune.ywpl == 2) return run_y_fwd_w<T, MY, 2, KIND>(p, pd, nrhs, s);
   }
-  return run_y_fwd_w<T, MY, 1>(p, pd, nrhs, s);
+  return run_y_fwd_w<T, MY, 1, KIND>(p, pd, nrhs, s);
 }
 
-template <typename T, int MY>
+template <typename T, int MY, int KIND = kDst>
 static hipError_t run_y_back_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   if constexpr (MY >= 512) {
-    if (p->tune.ywpl == 2) return run_y_back_w<T, MY, 2>(p, pd, nrhs, s);
+    if (p->tune.ywpl == 2) return run_y_back_w<T, MY, 2, KIND>(p, pd, nrhs, s);
   }
-  return run_y_back_w<T, MY, 1>(p, pd, nrhs, s);
+  return run_y_back_w<T, MY, 1, KIND>(p, pd, nrhs, s);
 }
 
 #define CS3D_DISPATCH(fn, M, ...)                 \
@@ -591,25 +634,55 @@ static hipError_t run_y_back_t(const cs3d_plan p, const ProbDev& pd, int nrhs, h
     default: return fn<T, 0>(__VA_ARGS__);        \
   }
 
+// the cosine transforms of Neumann sides (FP64; lines of at most 1023 nodes, so M <= 512)
+#define CS3D_DISPATCH_DCT(fn, M, ...)                  \
+  switch (M) {                                         \
+    case 64: return fn<double, 64, kDct>(__VA_ARGS__);   \
+    case 128: return fn<double, 128, kDct>(__VA_ARGS__); \
+    case 256: return fn<double, 256, kDct>(__VA_ARGS__); \
+    case 512: return fn<double, 512, kDct>(__VA_ARGS__); \
+    case 0: return fn<double, 0, kDct>(__VA_ARGS__);     \
+    default: return hipErrorInvalidValue;              \
+  }
+
 template <typename T>
 static hipError_t run_x_fwd(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->neu) { CS3D_DISPATCH_DCT(run_x_fwd_t, p->fx, p, pd, nrhs, s) }
+  }
   CS3D_DISPATCH(run_x_fwd_t, p->fx, p, pd, nrhs, s)
 }
 template <typename T>
 static hipError_t run_x_inv(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->neu) { CS3D_DISPATCH_DCT(run_x_inv_t, p->fx, p, pd, nrhs, s) }
+  }
   CS3D_DISPATCH(run_x_inv_t, p->fx, p, pd, nrhs, s)
 }
 template <typename T>
 static hipError_t run_y_fwd(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->neu) { CS3D_DISPATCH_DCT(run_y_fwd_t, p->fy, p, pd, nrhs, s) }
+  }
   CS3D_DISPATCH(run_y_fwd_t, p->fy, p, pd, nrhs, s)
 }
 template <typename T>
 static hipError_t run_y_back(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->neu) { CS3D_DISPATCH_DCT(run_y_back_t, p->fy, p, pd, nrhs, s) }
+  }
   CS3D_DISPATCH(run_y_back_t, p->fy, p, pd, nrhs, s)
 }
 #undef CS3D_DISPATCH
+#undef CS3D_DISPATCH_DCT
 
 static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if (p->neu) {
+    const dim3 grid((p->d.nx * p->d.ny + 255) / 256, p->d.nz, nrhs);
+    if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rhs_sides, grid, dim3(256), 0, s, pd);
+    return hipGetLastError();
+  }
   const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
@@ -656,10 +729,11 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.sinx = p->dsinx;
   pd.siny = p->dsiny;
   pd.f = f;
-  pd.f_stride = (long long)(p->d.nx + 2) * (p->d.ny + 2) * (p->d.nz + 2);
+  const int cx = p->neu ? p->d.nx : p->d.nx + 2, cy = p->neu ? p->d.ny : p->d.ny + 2;  // closed grid
+  pd.f_stride = (long long)cx * cy * (p->d.nz + 2);
   pd.glo = glo;
   pd.ghi = ghi;
-  pd.g_stride = (long long)(p->d.nx + 2) * (p->d.ny + 2);
+  pd.g_stride = (long long)cx * cy;
   pd.F = F;
   pd.u = u;
   pd.u_stride = (long long)p->d.nx * p->d.ny * p->d.nz;
@@ -863,7 +937,7 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
   if (dev_r == dev_u || dev_r == dev_f) return CS3D_E_INVAL;
-  if (p->cplx) return CS3D_E_UNSUPPORTED;
+  if (p->cplx || p->neu) return CS3D_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)hip_stream;
   // F (with the lift) goes into r, then r = F - A U in place
   const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
@@ -1259,7 +1333,7 @@ extern "C" cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hi
     const cs3d_status st = validate(&d);
     if (st != CS3D_OK) return st;
     if (d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
-    if (d.precision != CS3D_FP64 || d.k2_im) return CS3D_E_UNSUPPORTED;
+    if (d.precision != CS3D_FP64 || d.k2_im || d.sides != CS3D_SIDES_DIRICHLET) return CS3D_E_UNSUPPORTED;
   }
   cs3d_batch b = new (std::nothrow) cs3d_batch_s();
   if (!b) return CS3D_E_NOMEM;

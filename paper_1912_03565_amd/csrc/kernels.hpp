@@ -72,44 +72,46 @@ struct ProbDev {
 };
 
 // ---------------------------------------------------------------------------
-// Line transform selection: M = N+1 for the FFT path, 0 for dense sine sums.
+// Line transform selection: the FFT length M (N+1 for the sine transform, N-1 for the
+// cosine transform of Neumann sides), 0 for dense sums; KIND kDst or kDct.
 // ---------------------------------------------------------------------------
-template <int M, int WPL>
+template <int M, int WPL, int KIND = kDst>
 struct Tx {
-  static constexpr int NS = FftGeom<M, WPL>::R;
+  static constexpr int NS = fft_out_slots<M, WPL, KIND>();
 };
-template <int WPL>
-struct Tx<0, WPL> {
+template <int WPL, int KIND>
+struct Tx<0, WPL, KIND> {
   static constexpr int NS = kDenseSlots;
 };
 
-template <typename T, int M, int WPL>
-using TxOut = T[Tx<M, WPL>::NS];
+template <typename T, int M, int WPL, int KIND = kDst>
+using TxOut = T[Tx<M, WPL, KIND>::NS];
 
-template <typename T, int M, int WPL, bool BLOCK_SYNC = false>
-__device__ __forceinline__ void line_dst(T* buf, int N, TxOut<T, M, WPL>& out, int tl, const cx<T>* tab,
-                                         const double* sintab, const T* src = nullptr) {
+template <typename T, int M, int WPL, bool BLOCK_SYNC = false, int KIND = kDst>
+__device__ __forceinline__ void line_dst(T* buf, int N, TxOut<T, M, WPL, KIND>& out, int tl, const cx<T>* tab,
+                                         const double* trig, const T* src = nullptr) {
   if constexpr (M == 0) {
-    dst_dense<T>(buf, N, out, tl, sintab, src);
+    dst_dense<T, KIND>(buf, N, out, tl, trig, src);
     if constexpr (BLOCK_SYNC) __syncthreads();
   } else {
-    dst_fft<T, M, WPL, BLOCK_SYNC>(buf, out, tl, tab, src);
+    dst_fft<T, M, WPL, KIND, BLOCK_SYNC>(buf, out, tl, tab, src);
   }
 }
 
-template <int M, int WPL>
+template <int M, int WPL, int KIND = kDst>
 __device__ __forceinline__ int line_mode(int tl, int s, int N) {
   if constexpr (M == 0) {
     return dense_mode(tl, s, N);
   } else {
-    return fft_mode<M, WPL>(tl, s);
+    return fft_mode<M, WPL, KIND>(tl, s);
   }
 }
 
-// elements of T in one line buffer
+// elements of T in one line buffer (it also holds the line at positions 0..N)
 template <typename T, int M, int WPL>
 __host__ __device__ constexpr int line_buf_elems(int N) {
-  return M ? fft_buf_elems<T, M, WPL>() : ((N + 1 + 63) / 64) * 64;
+  const int line = ((N + 1 + 63) / 64) * 64;
+  return M ? (fft_buf_elems<T, M, WPL>() > line ? fft_buf_elems<T, M, WPL>() : line) : line;
 }
 
 // twiddle table bytes (FFT path only)
@@ -437,6 +439,85 @@ __global__ void __launch_bounds__(256) k_rhs_faces(ProbDev p, int axis) {
 }
 
 // ---------------------------------------------------------------------------
+// RHS operator for Neumann sides: p.nx, p.ny count the nodes of an x/y plane (the
+// side nodes are unknowns), f is the closed grid with rows of p.nx values, and a
+// value beyond a side is the mirror image about it (f_{-1} = f_1, f_{-2} = f_2).
+// The x and y differences are therefore all central; the z ones as in k_rhs (the
+// one-sided fourth difference on the first and last plane), then the lift of the
+// z-face data through the in-plane 9-point weights, mirrored alike.
+// One point per thread; grid: (ceil(nx ny / 256), nz, right-hand sides).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int mirror(int i, int n) { return i < 0 ? -i : (i >= n ? 2 * (n - 1) - i : i); }
+
+__global__ void __launch_bounds__(256) k_rhs_sides(ProbDev p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.nx * p.ny) return;
+  const int i = e % p.nx, j = e / p.nx, l = 1 + blockIdx.y, r = blockIdx.z;
+  const int nx = p.nx, ny = p.ny;
+  const double* f = p.f + r * p.f_stride;
+  auto at = [&](int di, int dj, int dl) -> double {
+    return f[mirror(i + di, nx) + (long long)nx * (mirror(j + dj, ny) + (long long)ny * (l + dl))];
+  };
+  const double hz2 = p.hz * p.hz;
+  const double f0 = at(0, 0, 0);
+  double F;
+  if (p.scheme == kHelm2) {
+    F = hz2 * f0;
+  } else {
+    const double d2x = at(-1, 0, 0) - 2.0 * f0 + at(1, 0, 0);
+    const double d2y = at(0, -1, 0) - 2.0 * f0 + at(0, 1, 0);
+    const double d2z = at(0, 0, -1) - 2.0 * f0 + at(0, 0, 1);
+    if (p.scheme == kHelm4) {
+      F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
+    } else if (p.scheme == kCd4) {
+      const double d1z = 0.5 * (at(0, 0, 1) - at(0, 0, -1));
+      F = hz2 * (f0 + d2x * (1.0 / 12.0) + d2y * (1.0 / 12.0) + (p.hz * p.gamma * d1z + d2z) * (1.0 / 12.0));
+    } else {
+      // 6th order: f + sum d2/12 - sum d4/240 + sum d2d2/90 - h^2 k^2 f/20 + h^3 (k^2)_z d1z/60
+      const double h = p.hz, kl = p.k2[l], kzl = p.k2z[l];
+      const double d4x = at(-2, 0, 0) - 4.0 * (at(-1, 0, 0) + at(1, 0, 0)) + 6.0 * f0 + at(2, 0, 0);
+      const double d4y = at(0, -2, 0) - 4.0 * (at(0, -1, 0) + at(0, 1, 0)) + 6.0 * f0 + at(0, 2, 0);
+      double d4z;
+      if (l == 1) {
+        d4z = 2.0 * at(0, 0, -1) - 9.0 * f0 + 16.0 * at(0, 0, 1) - 14.0 * at(0, 0, 2) + 6.0 * at(0, 0, 3) -
+              at(0, 0, 4);
+      } else if (l == p.nz) {
+        d4z = 2.0 * at(0, 0, 1) - 9.0 * f0 + 16.0 * at(0, 0, -1) - 14.0 * at(0, 0, -2) + 6.0 * at(0, 0, -3) -
+              at(0, 0, -4);
+      } else {
+        d4z = at(0, 0, -2) - 4.0 * (at(0, 0, -1) + at(0, 0, 1)) + 6.0 * f0 + at(0, 0, 2);
+      }
+      // products of second differences over the three coordinate planes
+      auto d2d2 = [&](int ax, int bx) -> double {
+        double acc = 0.0;
+        for (int da = -1; da <= 1; ++da)
+          for (int db = -1; db <= 1; ++db) {
+            const double wa = da ? 1.0 : -2.0, wb = db ? 1.0 : -2.0;
+            int d[3] = {0, 0, 0};
+            d[ax] = da;
+            d[bx] = db;
+            acc += wa * wb * at(d[0], d[1], d[2]);
+          }
+        return acc;
+      };
+      const double sx = d2d2(0, 1) + d2d2(0, 2) + d2d2(1, 2);
+      const double d1z = 0.5 * (at(0, 0, 1) - at(0, 0, -1));
+      F = h * h * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - (d4x + d4y + d4z) * (1.0 / 240.0) + sx * (1.0 / 90.0) -
+                   h * h * kl * f0 * (1.0 / 20.0) + h * h * h * kzl * d1z * (1.0 / 60.0));
+    }
+  }
+  // lift of the z-face data (both faces when nz = 1)
+  auto plane9m = [&](const double* w, const double* P) -> double {
+    auto g = [&](int di, int dj) { return P[mirror(i + di, nx) + (long long)nx * mirror(j + dj, ny)]; };
+    return w[0] * (g(-1, -1) + g(1, -1) + g(-1, 1) + g(1, 1)) + w[1] * (g(-1, 0) + g(1, 0)) +
+           w[2] * (g(0, -1) + g(0, 1)) + w[3] * g(0, 0);
+  };
+  if (l == 1 && p.glo) F -= plane9m(p.W + 0, p.glo + r * p.g_stride);
+  if (l == p.nz && p.ghi) F -= plane9m(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride);
+  p.u[r * p.u_stride + i + (long long)nx * (j + (long long)ny * (l - 1))] = F;
+}
+
+// ---------------------------------------------------------------------------
 // K1: DST along x of 8 lines of F, transposed store into y-lines.  Persistent:
 // each workgroup walks tiles t = t0, t0 + gridDim.x, ... (t0 its XCD-ordered index; 8 y-lines
 // of one plane of one right-hand side each) and loads the rows of its next tile
@@ -462,11 +543,11 @@ __device__ __forceinline__ XTile decode_xtile(const ProbDev& p, int t, int w) {
   return x;
 }
 
-template <typename T, int MX>
+template <typename T, int MX, int KIND = kDst>
 __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MX, 1>::NS;
+  constexpr int NS = Tx<MX, 1, KIND>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
@@ -496,13 +577,13 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
     if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
     __syncthreads();  // also publishes the twiddle table on the first pass
     T out[NS];
-    if (x.active) line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
+    if (x.active) line_dst<T, MX, 1, false, KIND>(buf, p.nx, out, lane, tab, p.sinx);
     __syncthreads();
     // tile[jj][n], n = 1..nx, odd row stride
     if (x.active) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const int n = line_mode<MX, 1>(lane, s, p.nx);
+        const int n = line_mode<MX, 1, KIND>(lane, s, p.nx);
         if (n > 0) smem[w * ts + n] = out[s];
       }
     } else {
@@ -546,17 +627,18 @@ __device__ __forceinline__ void flush_stats(const ProbDev& p, double minpiv, uns
 template <int MY>
 constexpr int default_wpl() { return MY == 1024 ? 2 : 1; }
 
-template <int MY, int WPL_ = default_wpl<MY>()>
+template <int MY, int WPL_ = default_wpl<MY>(), int KIND = kDst>
 struct YCfg {
   static constexpr int WPL = WPL_;
   static constexpr int LANES = 64 * WPL;
   static constexpr int LPB = kBlockY / LANES;  // lines (x-modes) per workgroup
-  static constexpr int NS = Tx<MY, WPL>::NS;
-  static constexpr int NLD = (MY ? MY : 1024) / LANES;  // line values loaded per lane
+  static constexpr int NS = Tx<MY, WPL, KIND>::NS;
+  // line values loaded per lane (positions 0..N; N = M + 1 for the cosine transform)
+  static constexpr int NLD = ((MY ? MY + (KIND == kDct ? 2 : 0) : 1024) + LANES - 1) / LANES;
   // most right-hand sides one workgroup carries: their tridiagonal systems share the
   // eigenvalues and pivots (formed once per plane and mode) and c' (read once in the
   // back pass); one where a lane holds 16 modes (register budget)
-  static constexpr int NRMAX = NS <= 8 ? 4 : 1;
+  static constexpr int NRMAX = (NS <= 8 && KIND == kDst) ? 4 : 1;
 };
 
 // twiddle tables of a y pass, loaded by the whole block (a barrier follows)
@@ -577,9 +659,9 @@ __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load)
 // every mode are formed with the first of them and applied to all (the LU of Section
 // 3.6 does not depend on the right-hand side).  The workgroup of r0 = 0 stores c' and
 // records the pivots.
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
-  using C = YCfg<MY, WPL>;
+  using C = YCfg<MY, WPL, KIND>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
@@ -625,7 +707,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       if (r + 1 < nr) fetch(l, r + 1);
       else if (l < p.nz) fetch(l + 1, 0);
       T out[NS];
-      line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
       if (r == 0) {
         // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
         const double* Ll = p.LC + (l - 1) * 12;
@@ -636,7 +718,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
         if (active) {
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            const int m = line_mode<MY, WPL>(tl, s, p.ny);
+            const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
             if (m > 0) {
               const double sm = p.cty[m - 1];
               const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
@@ -653,7 +735,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       if (active) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const int m = line_mode<MY, WPL>(tl, s, p.ny);
+          const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
           if (m > 0) {
             dp[r][s] = ((double)out[s] - lmv[s] * dp[r][s]) * inv[s];
             line_p[m] = (T)dp[r][s];
@@ -667,22 +749,22 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
 }
 
 // grid: (line groups, groups of NR right-hand sides)
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
   const int r0 = blockIdx.y * NR;
-  yfwd_block<T, MY, WPL, NR>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
+  yfwd_block<T, MY, WPL, NR, KIND>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
 // K3: back substitution + inverse DST along y, the right-hand sides of a workgroup
 // sharing each read of c'.
 // ---------------------------------------------------------------------------
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
-  using C = YCfg<MY, WPL>;
+  using C = YCfg<MY, WPL, KIND>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
@@ -696,7 +778,7 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
   int mpos[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    mpos[s] = active ? line_mode<MY, WPL>(tl, s, p.ny) : -1;
+    mpos[s] = active ? line_mode<MY, WPL, KIND>(tl, s, p.ny) : -1;
 #pragma unroll
     for (int r = 0; r < NR; ++r) Wn[r][s] = 0.0;
   }
@@ -726,7 +808,7 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         if (mpos[s] > 0) Wn[r][s] = (double)pd[s] - pc[s] * Wn[r][s];
-      if constexpr (MY != 0) {
+      if constexpr (MY != 0 && KIND == kDst) {
         // modes 2q and 2q+1 of a lane are adjacent: one 16-byte store per pair (the
         // slot of mode 0 is written but never read)
         if (tl < FftGeom<MY, WPL>::L) {
@@ -752,7 +834,7 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
       }
       if (r == 0 && l > 1) fetch_c(l - 1, pcn);
       T out[NS];
-      line_dst<T, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         if (mpos[s] > 0) line_p[mpos[s]] = out[s];
@@ -763,13 +845,13 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
   }
 }
 
-template <typename T, int MY, int WPL, int NR>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
   const int r0 = blockIdx.y * NR;
-  yback_block<T, MY, WPL, NR>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
+  yback_block<T, MY, WPL, NR, KIND>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,11 +865,11 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
 // K4 register prefetch of the next tile (on: the loads of the next tile fly during the transform)
 constexpr bool kInvPrefetch = CS3D_INV_PREFETCH != 0;
 
-template <typename T, int MX>
+template <typename T, int MX, int KIND = kDst>
 __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  constexpr int NS = Tx<MX, 1>::NS;
+  constexpr int NS = Tx<MX, 1, KIND>::NS;
   constexpr int NT = (1023 * kTileJ + 64 * kTileJ - 1) / (64 * kTileJ);  // segment values per thread
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
@@ -828,12 +910,12 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
     // the transform reads its input straight from tile row w; the workgroup barrier
     // inside separates those reads from the exchanges that overlay the tile
     T out[NS];
-    line_dst<T, MX, 1, true>(buf, p.nx, out, lane, tab, p.sinx, smem + w * ts);
+    line_dst<T, MX, 1, true, KIND>(buf, p.nx, out, lane, tab, p.sinx, smem + w * ts);
     if (x.active) {
       double* u = p.u + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const int i = line_mode<MX, 1>(lane, s, p.nx);
+        const int i = line_mode<MX, 1, KIND>(lane, s, p.nx);
         if (i > 0) u[i - 1] = p.accumulate ? u[i - 1] + p.scale * (double)out[s] : p.scale * (double)out[s];
       }
     }

@@ -32,6 +32,18 @@
 //
 // Dense path (any N <= 1024).  Each lane sums S_k for its modes k directly, using a
 // table sin(pi r/M), r < 2M, in global memory.
+//
+// DCT-I (Neumann sides).  With unknowns on the side nodes too, a line holds
+// x_0..x_M (N = M + 1 values) and the even reflection about its end nodes is
+// diagonalised by C_k = sum_{n=0}^{M} e_n x_n cos(pi k n/M), k = 0..M, with
+// e_0 = e_M = 1/2 and e_n = 1 otherwise; C applied twice is M/2 times the identity.
+// For n = 0..M-1 let a_n = x_n + x_{M-n}, b_n = x_n - x_{M-n} (a_0 = x_0 + x_M) and
+// w_n = a_n + i b_n e^{-i pi n/M}.  The even frequencies of the length-2M DFT of the
+// even extension give C_{2q} = Re(W_q)/2, the odd ones C_{2q+1} = Im(W_q)/2 (the
+// imaginary part of the odd sum cancels between n and M - n), with the same M-point
+// FFT as the sine transform.  Mode M comes from W_{M/2}, an extra slot of lane 0.
+// Both kinds keep a line at buffer positions 1..N: for the sine transform position n
+// holds x_n, for the cosine transform x_{n-1}; outputs go to the same positions.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -421,23 +433,41 @@ __device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, 
 // tl is the lane index within the line (0 <= tl < 64 WPL).  On return, lane tl < L
 // holds out[s] = S_m for m = fft_mode<M, WPL>(tl, s); buf is clobbered.  All lanes
 // of the line's waves must call it (lanes tl >= L only take part in the syncs).
-template <typename T, int M, int WPL, bool BLOCK_SYNC = false>
-__device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl, const cx<T>* tab,
-                                        const T* src = nullptr) {
+// transform kinds: DST-I (Dirichlet sides) and DCT-I (Neumann sides)
+constexpr int kDst = 0, kDct = 1;
+
+// output slots per lane of the FFT path: R, and for the cosine transform one more (mode M)
+template <int M, int WPL, int KIND>
+__host__ __device__ constexpr int fft_out_slots() {
+  return FftGeom<M, WPL>::R + (KIND == kDct ? 1 : 0);
+}
+
+template <typename T, int M, int WPL, int KIND, bool BLOCK_SYNC = false>
+__device__ __forceinline__ void dst_fft(T* buf, T (&out)[fft_out_slots<M, WPL, KIND>()], int tl,
+                                        const cx<T>* tab, const T* src = nullptr) {
   constexpr int R = FftGeom<M, WPL>::R, L = FftGeom<M, WPL>::L;
   LineRegs<T, M, WPL> v;
   if (tl < L) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int n = tl + L * s;
-      if (n == 0) {
-        v[s] = {(T)0, (T)0};
+      if constexpr (KIND == kDst) {
+        if (n == 0) {
+          v[s] = {(T)0, (T)0};
+        } else {
+          const T a = src ? src[n] : buf[n];
+          const T b = src ? src[M - n] : buf[M - n];
+          const T u = a - b, z = a + b;
+          const cx<T> t = tab[n];  // (cos, -sin)(pi n/M)
+          v[s] = {u - z * t.im, z * t.re};
+        }
       } else {
-        const T a = src ? src[n] : buf[n];
-        const T b = src ? src[M - n] : buf[M - n];
-        const T u = a - b, z = a + b;
-        const cx<T> t = tab[n];  // (cos, -sin)(pi n/M)
-        v[s] = {u - z * t.im, z * t.re};
+        // x_n at position n + 1
+        const T a = src ? src[1 + n] : buf[1 + n];
+        const T b = src ? src[1 + M - n] : buf[1 + M - n];
+        const T z = a + b, u = a - b;
+        const cx<T> t = tab[n];
+        v[s] = {z - u * t.im, u * t.re};
       }
     }
   }
@@ -450,18 +480,30 @@ __device__ __forceinline__ void dst_fft(T* buf, LineOut<T, M, WPL>& out, int tl,
     fft_run<T, M, WPL>(v, buf, tl, tab + M);
 #pragma unroll
     for (int s = 0; s < R / 2; ++s) {
-      out[2 * s] = (T)-0.5 * v[s].im;
-      out[2 * s + 1] = (T)0.5 * v[s].re;
+      if constexpr (KIND == kDst) {
+        out[2 * s] = (T)-0.5 * v[s].im;
+        out[2 * s + 1] = (T)0.5 * v[s].re;
+      } else {
+        out[2 * s] = (T)0.5 * v[s].re;
+        out[2 * s + 1] = (T)0.5 * v[s].im;
+      }
     }
+    if constexpr (KIND == kDct) out[R] = (T)0.5 * v[R / 2].re;  // C_M (lane 0: W_{M/2})
   }
 }
 
-template <int M, int WPL>
+// buffer position of output slot s of lane tl (-1: no mode)
+template <int M, int WPL, int KIND = kDst>
 __device__ __forceinline__ int fft_mode(int tl, int s) {
-  constexpr int L = FftGeom<M, WPL>::L;
+  constexpr int L = FftGeom<M, WPL>::L, R = FftGeom<M, WPL>::R;
   if (tl >= L) return -1;
-  const int m = 2 * (tl + L * (s >> 1)) + (s & 1);
-  return (m >= 1 && m <= M - 1) ? m : -1;
+  if constexpr (KIND == kDct) {
+    if (s == R) return tl == 0 ? M + 1 : -1;
+    return 2 * (tl + L * (s >> 1)) + (s & 1) + 1;
+  } else {
+    const int m = 2 * (tl + L * (s >> 1)) + (s & 1);
+    return (m >= 1 && m <= M - 1) ? m : -1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -470,20 +512,35 @@ __device__ __forceinline__ int fft_mode(int tl, int s) {
 // ---------------------------------------------------------------------------
 constexpr int kDenseSlots = 16;
 
-template <typename T>
+// KIND = kDct: out[s] = C_k, k = lane + 64 s (position k + 1), with trig[r] = cos(pi r/M),
+// M = N - 1; x_n is read from position n + 1.
+template <typename T, int KIND = kDst>
 __device__ __forceinline__ void dst_dense(const T* buf, int N, T (&out)[kDenseSlots], int lane,
-                                          const double* __restrict__ sintab, const T* src = nullptr) {
-  const int twoM = 2 * (N + 1);
+                                          const double* __restrict__ trig, const T* src = nullptr) {
+  const int M = KIND == kDst ? N + 1 : N - 1;
+  const int twoM = 2 * M;
 #pragma unroll
   for (int s = 0; s < kDenseSlots; ++s) {
-    const int k = 1 + lane + 64 * s;
+    const int pos = 1 + lane + 64 * s;
     T acc = (T)0;
-    if (k <= N) {
+    if (pos <= N) {
+      const int k = KIND == kDst ? pos : pos - 1;
       int idx = 0;
-      for (int n = 1; n <= N; ++n) {
-        idx += k;
-        if (idx >= twoM) idx -= twoM;
-        acc += (src ? src[n] : buf[n]) * (T)sintab[idx];
+      if constexpr (KIND == kDst) {
+        for (int n = 1; n <= N; ++n) {
+          idx += k;
+          if (idx >= twoM) idx -= twoM;
+          acc += (src ? src[n] : buf[n]) * (T)trig[idx];
+        }
+      } else {
+        // end nodes with weight 1/2: x_0 (cos 0 = 1) and x_M (cos(pi k) = (-1)^k)
+        const T x0 = src ? src[1] : buf[1], xm = src ? src[N] : buf[N];
+        acc = (T)0.5 * (x0 + ((k & 1) ? -xm : xm));
+        for (int n = 1; n < M; ++n) {
+          idx += k;
+          if (idx >= twoM) idx -= twoM;
+          acc += (src ? src[1 + n] : buf[1 + n]) * (T)trig[idx];
+        }
       }
     }
     out[s] = acc;

@@ -42,6 +42,7 @@ class Desc(ctypes.Structure):
         ("k2_im", ctypes.POINTER(ctypes.c_double)),
         ("k2_z_im", ctypes.POINTER(ctypes.c_double)),
         ("k2_zz_im", ctypes.POINTER(ctypes.c_double)),
+        ("sides", ctypes.c_int),
     ]
 
 

@@ -46,8 +46,11 @@ def _aligned_workspace(nbytes, device):
     return buf, buf.data_ptr() + off
 
 
+SIDES = {"dirichlet": 0, "neumann": 1}
+
+
 def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
-               weights=None, precision="fp64", refine_steps=2, max_rhs=1):
+               weights=None, precision="fp64", refine_steps=2, max_rhs=1, sides="dirichlet"):
     """cs3d_desc and the host arrays it points to (keep them alive during the call)."""
     keep = []
     d = N.Desc()
@@ -71,6 +74,7 @@ def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, g
     d.precision = N.PRECISIONS[precision]
     d.refine_steps = int(refine_steps)
     d.max_rhs = int(max_rhs)
+    d.sides = SIDES[sides]
     return d, keep
 
 
@@ -79,8 +83,10 @@ class Plan:
 
     def __init__(self, nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None,
                  gamma=0.0, weights=None, precision="fp64", refine_steps=2, max_rhs=1,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, sides="dirichlet"):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        # Neumann sides: the side nodes are unknowns, a solution plane has (ny+2) x (nx+2) nodes
+        self.sides = sides
         self.scheme = scheme
         self.precision = precision
         # complex k: every field is planar, (nrhs, 2, ...) = real and imaginary parts
@@ -88,7 +94,7 @@ class Plan:
         self.max_rhs = int(max_rhs)
         self.device = torch.device(device)
         d, keep = _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2, k2_z, k2_zz, gamma, weights,
-                             precision, refine_steps, max_rhs)
+                             precision, refine_steps, max_rhs, sides)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             N.check("cs3d_plan_create",
@@ -105,6 +111,8 @@ class Plan:
         return self._lead(nrhs) + (self.nz + 2, self.ny + 2, self.nx + 2)
 
     def interior_shape(self, nrhs):
+        if self.sides == "neumann":
+            return self._lead(nrhs) + (self.nz, self.ny + 2, self.nx + 2)
         return self._lead(nrhs) + (self.nz, self.ny, self.nx)
 
     def plane_shape(self, nrhs):
@@ -228,7 +236,7 @@ def plan_for_problem(p, precision="fp64", refine_steps=2, max_rhs=None, device="
                 k2=p.k2, k2_z=p.k2_z if p.scheme == "helm6" else None,
                 k2_zz=p.k2_zz if p.scheme == "helm6" else None, gamma=p.gamma, weights=weights,
                 precision=precision, refine_steps=refine_steps,
-                max_rhs=max_rhs or p.nrhs, device=device)
+                max_rhs=max_rhs or p.nrhs, device=device, sides=getattr(p, "sides", "dirichlet"))
 
 
 class Batch:

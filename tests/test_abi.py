@@ -169,3 +169,36 @@ def test_complex_k_validation(N, case):
     plan = ctypes.c_void_p()
     assert N.lib.cs3d_plan_create(ctypes.byref(d), None, ctypes.byref(plan)) == want
     assert not plan.value
+
+
+@pytest.mark.parametrize("case", ["mixed", "complex", "too_long_x", "too_long_y", "bad_value", "batch"])
+def test_neumann_sides_validation(N, case):
+    """Neumann sides: FP64 plans with real k and lines of at most 1023 nodes."""
+    d = _desc(N, n=(63, 63, 63))
+    d.sides = 1
+    want = N.E_UNSUPPORTED
+    if case == "mixed":
+        d.precision = N.PRECISIONS["mixed"]
+    elif case == "complex":
+        im = np.full(d.nz + 2, 0.5)
+        d._keep.append(im)
+        d.k2_im = d.k2_z_im = d.k2_zz_im = im.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    elif case == "too_long_x":
+        d.nx = 1022
+        want = N.E_INVAL
+    elif case == "too_long_y":
+        d.ny = 1022
+        want = N.E_INVAL
+    elif case == "bad_value":
+        d.sides = 2
+        want = N.E_INVAL
+    if case == "batch":
+        descs = (N.Desc * 1)()
+        descs[0] = d
+        b = ctypes.c_void_p()
+        assert N.lib.cs3d_batch_create(1, descs, None, ctypes.byref(b)) == want
+        assert not b.value
+        return
+    plan = ctypes.c_void_p()
+    assert N.lib.cs3d_plan_create(ctypes.byref(d), None, ctypes.byref(plan)) == want
+    assert not plan.value
