@@ -135,6 +135,13 @@ __device__ __forceinline__ V opaque(V v) {
   return v;
 }
 
+// Read a plan table through the constant address space: the tables are never written
+// while a kernel runs, so uniform reads become scalar loads, which a wait for vector
+// memory operations (prefetched lines, stores) does not have to include.
+__device__ __forceinline__ double ctab(const double* t, int i) {
+  return ((const __attribute__((address_space(4))) double*)t)[i];
+}
+
 // ---------------------------------------------------------------------------
 // XCD-aware work order.  The 8 XCDs of the chip each have their own L2, and
 // workgroups are handed to them round-robin by linear index.  xcd_order maps the
@@ -672,12 +679,19 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
   }
   T* buf = smem + line * bufn;
   const double ctn = active ? p.ctx[n - 1] : 0.0;
-  double cp[NS], dp[NR][NS], lmv[NS], inv[NS];
+  // s_m of each slot's mode is the same on every plane: held in registers where they allow
+  // it (FP64, one right-hand side per workgroup), else read per plane
+  constexpr bool kHoistS = sizeof(T) == 8 && NR == 1;
+  double cp[NS], dp[NR][NS], lmv[NS], inv[NS], smv[kHoistS ? NS : 1];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     cp[s] = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) dp[r][s] = 0.0;
+    if constexpr (kHoistS) {
+      const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
+      smv[s] = p.cty[(active && m > 0 ? m : 1) - 1];
+    }
   }
   double minpiv = 1.0e308;
   unsigned bad = 0;
@@ -685,12 +699,25 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
   const long long lstride = (long long)p.nx * p.ldy;
   const long long nbase = (long long)(active ? n - 1 : 0) * p.ldy;
   T* G0 = reinterpret_cast<T*>(p.G) + r0 * p.G_stride;
-  // prefetch of the line of the next (plane, right-hand side) pair
+  // prefetch of the line of the next (plane, right-hand side) pair.  Every lane issues
+  // every load and every store of a step (positions outside the line, and the whole of
+  // an inactive line, go to position 0 of the row, which no pass reads as data), so the
+  // number of memory operations in flight is fixed and the wait for the prefetched line
+  // does not also wait for the stores of the step before.
   T pre[C::NLD];
   auto fetch = [&](int l, int r) {
-    const T* src = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase + opaque(tl);
+    const T* row = G0 + r * p.G_stride + (long long)(l - 1) * lstride + nbase;
+    const int tlo = opaque(tl);
 #pragma unroll
-    for (int s = 0; s < C::NLD; ++s) pre[s] = (active && tl + C::LANES * s <= p.ny) ? src[C::LANES * s] : (T)0;
+    for (int s = 0; s < C::NLD; ++s) {
+      const int e = tlo + C::LANES * s;
+      if constexpr (kHoistS) {
+        // (opaque: one load per slot, not a shared load of position 0 plus copies)
+        pre[s] = row[opaque((active && e <= p.ny) ? e : 0)];  // an inactive line is filled with zeros below
+      } else {
+        pre[s] = (active && e <= p.ny) ? row[e] : (T)0;
+      }
+    }
   };
   fetch(1, 0);
   for (int l = 1; l <= p.nz; ++l) {
@@ -701,21 +728,39 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
 #pragma unroll
       for (int s = 0; s < C::NLD; ++s) {
         const int e = tl + C::LANES * s;
-        if (e <= p.ny) buf[e] = pre[s];
+        if constexpr (MY != 0 && KIND == kDst) {
+          buf[e] = active ? pre[s] : (T)0;  // e < M = N + 1: always a position of the line
+        } else {
+          if (e <= p.ny) buf[e] = active ? pre[s] : (T)0;
+        }
       }
       line_sync<WPL>();
       if (r + 1 < nr) fetch(l, r + 1);
       else if (l < p.nz) fetch(l + 1, 0);
-      T out[NS];
+      T out[NS] = {};  // lanes past the FFT's own take part with zeros
       line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
       if (r == 0) {
         // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
-        const double* Ll = p.LC + (l - 1) * 12;
-        const double bm = Ll[0] + ctn * Ll[1], am = Ll[2] + Ll[3] * ctn;
-        const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
-        const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
+        const int lc = (l - 1) * 12;
+        const double bm = ctab(p.LC, lc + 0) + ctn * ctab(p.LC, lc + 1), am = ctab(p.LC, lc + 2) + ctab(p.LC, lc + 3) * ctn;
+        const double b0 = ctab(p.LC, lc + 4) + ctn * ctab(p.LC, lc + 5), a0 = ctab(p.LC, lc + 6) + ctab(p.LC, lc + 7) * ctn;
+        const double bp = ctab(p.LC, lc + 8) + ctn * ctab(p.LC, lc + 9), ap = ctab(p.LC, lc + 10) + ctab(p.LC, lc + 11) * ctn;
         double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
-        if (active) {
+        if constexpr (kHoistS) {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
+            const bool valid = active && m > 0;
+            const double sm = smv[s];
+            const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+            const double piv = l0 - lm * cp[s];
+            if (lead && valid) record_pivot(piv, minpiv, bad);
+            inv[s] = 1.0 / piv;
+            lmv[s] = lm;
+            cp[s] = lpv * inv[s];
+            if (lead) Cl[valid ? m : 0] = cp[s];
+          }
+        } else if (active) {
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
@@ -732,7 +777,15 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
           }
         }
       }
-      if (active) {
+      if constexpr (kHoistS) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
+          const bool valid = active && m > 0;
+          dp[r][s] = ((double)out[s] - lmv[s] * dp[r][s]) * inv[s];
+          line_p[valid ? m : 0] = (T)dp[r][s];
+        }
+      } else if (active) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
@@ -993,9 +1046,13 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
   }
   double* buf = smem + line * bufn;
   const double ctn = active ? p.ctx[n - 1] : 0.0;
-  double cpr[NS], cpi[NS], dpr[NS], dpi[NS], orr[NS];
+  double cpr[NS], cpi[NS], dpr[NS], dpi[NS], orr[NS], smv[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) cpr[s] = cpi[s] = dpr[s] = dpi[s] = 0.0;
+  for (int s = 0; s < NS; ++s) {
+    cpr[s] = cpi[s] = dpr[s] = dpi[s] = 0.0;
+    const int m = line_mode<MY, WPL>(tl, s, p.ny);
+    smv[s] = p.cty[(active && m > 0 ? m : 1) - 1];  // s_m of the slot's mode, the same on every plane
+  }
   double minpiv = 1.0e308;
   unsigned bad = 0;
   const bool lead = (q == 0);
@@ -1026,8 +1083,13 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
 #pragma unroll
         for (int s = 0; s < NS; ++s) orr[s] = out[s];
       } else if (active) {
-        const double* Lr = p.LC + (l - 1) * 12;
-        const double* Li = p.LCi + (l - 1) * 12;
+        // plan tables through scalar loads (see ctab)
+        double Lr[12], Li[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          Lr[k] = ctab(p.LC, (l - 1) * 12 + k);
+          Li[k] = ctab(p.LCi, (l - 1) * 12 + k);
+        }
         double* Cr = p.C + (long long)(l - 1) * lstride + nbase;
         double* Cim = p.Ci + (long long)(l - 1) * lstride + nbase;
         double* d0 = G0 + (long long)(l - 1) * lstride + nbase;
@@ -1036,7 +1098,7 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
         for (int s = 0; s < NS; ++s) {
           const int m = line_mode<MY, WPL>(tl, s, p.ny);
           if (m > 0) {
-            const double sm = p.cty[m - 1];
+            const double sm = smv[s];
             // lambda^o = (Z + s_n B) + s_m (C + A s_n), real and imaginary parts
             const double lmr = (Lr[2] + Lr[3] * ctn) * sm + (Lr[0] + ctn * Lr[1]);
             const double lmi = (Li[2] + Li[3] * ctn) * sm + (Li[0] + ctn * Li[1]);
