@@ -296,7 +296,7 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
     const double* P0 = win[slot(l)];
     const double* Pm = win[slot(l - 1)];
     const double* Pp = win[slot(l + 1)];
-    const double kl = p.k2[l], kzl = p.k2z[l];
+    const double kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
     // y-neighbours: own registers inside the thread's rows, LDS outside
     auto y0v = [&](int k, int d) -> double {
       const int kk = k + d;
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(256) k_rhs_sides(ProbDev p) {
       F = hz2 * (f0 + d2x * (1.0 / 12.0) + d2y * (1.0 / 12.0) + (p.hz * p.gamma * d1z + d2z) * (1.0 / 12.0));
     } else {
       // 6th order: f + sum d2/12 - sum d4/240 + sum d2d2/90 - h^2 k^2 f/20 + h^3 (k^2)_z d1z/60
-      const double h = p.hz, kl = p.k2[l], kzl = p.k2z[l];
+      const double h = p.hz, kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
       const double d4x = at(-2, 0, 0) - 4.0 * (at(-1, 0, 0) + at(1, 0, 0)) + 6.0 * f0 + at(2, 0, 0);
       const double d4y = at(0, -2, 0) - 4.0 * (at(0, -1, 0) + at(0, 1, 0)) + 6.0 * f0 + at(0, 2, 0);
       double d4z;
@@ -1271,12 +1271,28 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
   fetch(pb, lb + 2);
   const int i = x0 + tx;
   double ss = 0.0;
-  auto compute = [&](int l) {
+  // F of the rows a thread owns, fetched two planes ahead like U; the weights come through
+  // scalar loads, so no wait in the stencil phase holds up the prefetched planes
+  double fA[kQRows], fB[kQRows];
+  auto fetchF = [&](double(&dst)[kQRows], int q) {
+#pragma unroll
+    for (int k = 0; k < kQRows; ++k) {
+      const int j = y0 + ty * kQRows + k;
+      dst[k] = (q <= le && i <= p.nx && j <= p.ny)
+                   ? Fi[r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (q - 1))]
+                   : 0.0;
+    }
+  };
+  fetchF(fA, lb);
+  fetchF(fB, lb + 1);
+  auto compute = [&](int l, const double(&fl)[kQRows]) {
     const double* Pm = win[(l + 2) % 3];
     const double* P0 = win[l % 3];
     const double* Pp = win[(l + 1) % 3];
-    const double* Wl = p.W + (l - 1) * 12;
-#pragma unroll 1
+    double w[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) w[q] = ctab(p.W, (l - 1) * 12 + q);
+#pragma unroll
     for (int k = 0; k < kQRows; ++k) {
       const int yl = ty * kQRows + k, j = y0 + yl;
       if (i > p.nx || j > p.ny) continue;
@@ -1286,12 +1302,12 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
 #pragma unroll
       for (int o = 0; o < 3; ++o) {
         const double* P = planes[o];
-        const double* w = Wl + 4 * o;
-        au += w[0] * (P[c - kQX - 1] + P[c - kQX + 1] + P[c + kQX - 1] + P[c + kQX + 1]) +
-              w[1] * (P[c - 1] + P[c + 1]) + w[2] * (P[c - kQX] + P[c + kQX]) + w[3] * P[c];
+        const double* wo = w + 4 * o;
+        au += wo[0] * (P[c - kQX - 1] + P[c - kQX + 1] + P[c + kQX - 1] + P[c + kQX + 1]) +
+              wo[1] * (P[c - 1] + P[c + 1]) + wo[2] * (P[c - kQX] + P[c + kQX]) + wo[3] * P[c];
       }
       const long long idx = r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
-      const double rr = Fi[idx] - au;
+      const double rr = fl[k] - au;
       R[idx] = rr;
       ss += rr * rr;
     }
@@ -1300,13 +1316,15 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
     stash(pa, l + 1);
     __syncthreads();
     if (l + 2 <= le) fetch(pa, l + 3);
-    compute(l);
+    compute(l, fA);
+    if (l + 2 <= le) fetchF(fA, l + 2);
     __syncthreads();
     if (l + 1 <= le) {
       stash(pb, l + 2);
       __syncthreads();
       if (l + 3 <= le) fetch(pb, l + 4);
-      compute(l + 1);
+      compute(l + 1, fB);
+      if (l + 3 <= le) fetchF(fB, l + 3);
       __syncthreads();
     }
   }
