@@ -549,15 +549,21 @@ static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
   return launch(k_fwd_x<T, MX, KIND>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 
-template <typename T, int MX, int KIND = kDst>
-static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+template <typename T, int MX, int KIND, bool ACC>
+static hipError_t run_x_inv_a(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX, KIND>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_inv_x<T, MX, KIND, ACC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = p->tune.xpersist ? resident_blocks(k_inv_x<T, MX, KIND>, 64 * kTileJ, lds, ntiles) : ntiles;
-  return launch(k_inv_x<T, MX, KIND>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_inv_x<T, MX, KIND, ACC>, 64 * kTileJ, lds, ntiles) : ntiles;
+  return launch(k_inv_x<T, MX, KIND, ACC>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+}
+
+// u = the result, or u += it for the corrections of the mixed path
+template <typename T, int MX, int KIND = kDst>
+static hipError_t run_x_inv_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  return pd.accumulate ? run_x_inv_a<T, MX, KIND, true>(p, pd, nrhs, s) : run_x_inv_a<T, MX, KIND, false>(p, pd, nrhs, s);
 }
 
 // grid: (line groups, groups of NR right-hand sides)

@@ -918,12 +918,16 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
 // K4 register prefetch of the next tile (on: the loads of the next tile fly during the transform)
 constexpr bool kInvPrefetch = CS3D_INV_PREFETCH != 0;
 
-template <typename T, int MX, int KIND = kDst>
+// ACC: u += the result (refinement corrections) instead of u = the result
+template <typename T, int MX, int KIND = kDst, bool ACC = false>
 __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 1, KIND>::NS;
-  constexpr int NT = (1023 * kTileJ + 64 * kTileJ - 1) / (64 * kTileJ);  // segment values per thread
+  // FIXED: as in k_fwd_x, a fixed number of loads and stores per lane and tile (sine FFT of
+  // 256..1024 points, plain stores)
+  constexpr bool FIXED = KIND == kDst && MX >= 256 && !ACC;
+  constexpr int NT = FIXED ? MX / 64 : (1023 * kTileJ + 64 * kTileJ - 1) / (64 * kTileJ);  // values per thread
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
@@ -938,11 +942,21 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
     const XTile x = decode_xtile(p, t, 0);
     const int tid = opaque((int)threadIdx.x);
     const int n0 = tid / kTileJ, jj = tid % kTileJ;
-    const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
-                 x.jt * kTileJ + (long long)n0 * p.ldy + jj;
-    const long long step = (long long)kXRows * p.ldy;
+    if constexpr (FIXED) {
+      const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
+                   x.jt * kTileJ + jj;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) pre[k] = (n0 + kXRows * k < p.nx) ? G[k * step] : (T)0;
+      for (int k = 0; k < NT; ++k) {
+        const int row = n0 + kXRows * k;
+        pre[k] = G[(long long)opaque(row < p.nx ? row : 0) * p.ldy];  // row M - 1: a valid stand-in
+      }
+    } else {
+      const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
+                   x.jt * kTileJ + (long long)n0 * p.ldy + jj;
+      const long long step = (long long)kXRows * p.ldy;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) pre[k] = (n0 + kXRows * k < p.nx) ? G[k * step] : (T)0;
+    }
   };
   int t = xcd_order(blockIdx.x, gridDim.x);
   if (kInvPrefetch && t < ntiles) fetch(t);
@@ -955,8 +969,13 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
       const int n0 = tid / kTileJ, jj = tid % kTileJ;
       T* row = smem + jj * ts + n0 + 1;
 #pragma unroll
-      for (int k = 0; k < NT; ++k)
-        if (n0 + kXRows * k < p.nx) row[kXRows * k] = pre[k];
+      for (int k = 0; k < NT; ++k) {
+        if constexpr (FIXED) {
+          row[kXRows * k] = pre[k];  // position M of the tile row is not read by the transform
+        } else {
+          if (n0 + kXRows * k < p.nx) row[kXRows * k] = pre[k];
+        }
+      }
     }
     __syncthreads();  // also publishes the twiddle table on the first pass
     if (kInvPrefetch && t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
@@ -969,7 +988,15 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int i = line_mode<MX, 1, KIND>(lane, s, p.nx);
-        if (i > 0) u[i - 1] = p.accumulate ? u[i - 1] + p.scale * (double)out[s] : p.scale * (double)out[s];
+        if constexpr (FIXED) {
+          // the one slot without a mode (lane 0, mode 0) writes u[0] with the value of its
+          // own slot 1 (mode 1), which stores it too
+          u[i > 0 ? i - 1 : 0] = p.scale * (double)(i > 0 ? out[s] : out[1]);
+        } else if constexpr (ACC) {
+          if (i > 0) u[i - 1] = u[i - 1] + p.scale * (double)out[s];
+        } else {
+          if (i > 0) u[i - 1] = p.scale * (double)out[s];
+        }
       }
     }
   }
