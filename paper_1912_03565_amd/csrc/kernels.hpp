@@ -135,6 +135,16 @@ __device__ __forceinline__ V opaque(V v) {
   return v;
 }
 
+// Settle prefetched registers: the wait for their loads happens here instead of where they
+// are first used.  Placed after a transform and before a phase of stores, it keeps the
+// wait (which also waits for every older memory operation) from covering those stores,
+// so they stay in flight while the next line or tile is filled.
+template <typename V, int N>
+__device__ __forceinline__ void settle(V (&a)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = opaque(a[k]);
+}
+
 // Read a plan table through the constant address space: the tables are never written
 // while a kernel runs, so uniform reads become scalar loads, which a wait for vector
 // memory operations (prefetched lines, stores) does not have to include.
@@ -572,6 +582,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   };
   int t = xcd_order(blockIdx.x, gridDim.x);
   if (t < ntiles) fetch(t);
+  settle(pre);  // (every path into the loop arrives with settled rows)
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
     __syncthreads();  // the previous tile's store phase is done with the LDS
@@ -597,6 +608,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
       for (int n = 1 + lane; n <= p.nx; n += 64) smem[w * ts + n] = (T)0;
     }
     __syncthreads();
+    settle(pre);  // the next tile's rows, fetched before the transform
     T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
     for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
       const int n0 = idx / kTileJ, jj = idx % kTileJ;
@@ -720,6 +732,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
     }
   };
   fetch(1, 0);
+  settle(pre);
   for (int l = 1; l <= p.nz; ++l) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -739,6 +752,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       else if (l < p.nz) fetch(l + 1, 0);
       T out[NS] = {};  // lanes past the FFT's own take part with zeros
       line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
+      settle(pre);  // the next line, fetched before the transform
       if (r == 0) {
         // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
         const int lc = (l - 1) * 12;
@@ -853,6 +867,8 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
   };
   fetch_d(p.nz, 0);
   fetch_c(p.nz, pc);
+  settle(pd);
+  settle(pc);
   for (int l = p.nz; l >= 1; --l) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -888,6 +904,8 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
       if (r == 0 && l > 1) fetch_c(l - 1, pcn);
       T out[NS];
       line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
+      settle(pd);  // d' and c' of the next step, fetched before the transform
+      settle(pcn);
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         if (mpos[s] > 0) line_p[mpos[s]] = out[s];
@@ -960,6 +978,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   };
   int t = xcd_order(blockIdx.x, gridDim.x);
   if (kInvPrefetch && t < ntiles) fetch(t);
+  settle(pre);
   for (; t < ntiles; t += gridDim.x) {
     const XTile x = decode_xtile(p, t, w);
     if (!kInvPrefetch) fetch(t);
@@ -983,6 +1002,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
     // inside separates those reads from the exchanges that overlay the tile
     T out[NS];
     line_dst<T, MX, 1, true, KIND>(buf, p.nx, out, lane, tab, p.sinx, smem + w * ts);
+    if (kInvPrefetch) settle(pre);  // the next tile's segments, fetched before the transform
     if (x.active) {
       double* u = p.u + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
 #pragma unroll
@@ -1093,6 +1113,7 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
     for (int s = 0; s < C::NLD; ++s) pre[s] = (active && tl + C::LANES * s <= p.ny) ? src[C::LANES * s] : 0.0;
   };
   fetch(1, 0);
+  settle(pre);
   for (int l = 1; l <= p.nz; ++l) {
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
@@ -1106,6 +1127,7 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
       else if (l < p.nz) fetch(l + 1, 0);
       double out[NS];
       line_dst<double, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      settle(pre);  // the next line, fetched before the transform
       if (part == 0) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) orr[s] = out[s];
@@ -1204,6 +1226,10 @@ __device__ __forceinline__ void yback_block_c(const ProbDev& p, int g, int q, do
     }
   };
   fetch(p.nz);
+  settle(pdr);
+  settle(pdi);
+  settle(pcr);
+  settle(pci);
   for (int l = p.nz; l >= 1; --l) {
     // W_l = d'_l - c'_l W_{l+1}
 #pragma unroll
@@ -1225,6 +1251,12 @@ __device__ __forceinline__ void yback_block_c(const ProbDev& p, int g, int q, do
       line_sync<WPL>();
       double out[NS];
       line_dst<double, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
+      if (part == 0) {  // d' and c' of the next plane, fetched before the transforms
+        settle(pdr);
+        settle(pdi);
+        settle(pcr);
+        settle(pci);
+      }
       double* dst = line0 + part * p.G_stride;
 #pragma unroll
       for (int s = 0; s < NS; ++s)
