@@ -80,7 +80,8 @@ typedef enum {
 typedef enum {
   CS3D_FP64 = 0,        /* every stage in FP64 */
   CS3D_MIXED_FP32 = 1   /* FP32 line transforms and FP32 intermediates, FP64 tridiagonal
-                           solves, FP64 27-point residual and refinement */
+                           solves, FP64 27-point residual (computed in FP64, handed to the
+                           FP32 correction solve in FP32) and FP64 update of u */
 } cs3d_precision;
 
 /* Conditions on the x and y faces. */

@@ -538,15 +538,24 @@ static int resident_blocks(KernelT kern, int threads, size_t lds, int ntiles) {
   return (int)(b < ntiles ? b : ntiles);
 }
 
-template <typename T, int MX, int KIND = kDst>
-static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+template <typename T, int MX, int KIND, typename TI>
+static hipError_t run_x_fwd_i(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX, KIND>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX, KIND, TI>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX, KIND>, 64 * kTileJ, lds, ntiles) : ntiles;
-  return launch(k_fwd_x<T, MX, KIND>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX, KIND, TI>, 64 * kTileJ, lds, ntiles) : ntiles;
+  return launch(k_fwd_x<T, MX, KIND, TI>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
+}
+
+// the input F is FP64, or FP32 for the residuals of the mixed path (pd.f32_input)
+template <typename T, int MX, int KIND = kDst>
+static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (pd.f32_input) return run_x_fwd_i<T, MX, KIND, float>(p, pd, nrhs, s);
+  }
+  return run_x_fwd_i<T, MX, KIND, double>(p, pd, nrhs, s);
 }
 
 template <typename T, int MX, int KIND, bool ACC>
@@ -848,14 +857,20 @@ static hipError_t run_rhs_cx(const cs3d_plan p, const ProbDev& pd, int nrhs, hip
 
 static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s);
 
-// r = F - A U and its squared norm into stats word `slot` (slot < 0: no norm)
-static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, double* R,
+// r = F - A U (FP64 arithmetic) and its squared norm into stats word `slot` (slot < 0: no
+// norm); r is stored as TR, or not at all when R is null
+template <typename TR>
+static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, TR* R,
                                 int nrhs, int slot, hipStream_t s) {
   const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kQTX - 1) / kQTX, (p->d.ny + kQTY - 1) / kQTY, nzc * nrhs);
   if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
   double* acc = slot >= 0 ? reinterpret_cast<double*>(p->dstats) + slot : nullptr;
-  hipLaunchKernelGGL(k_residual, grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
+  if (R) {
+    hipLaunchKernelGGL((k_residual<TR, true>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
+  } else {
+    hipLaunchKernelGGL((k_residual<TR, false>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
+  }
   return hipGetLastError();
 }
 
@@ -896,17 +911,22 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   } else {
     // FP32 transforms + FP64 tridiagonal solves, then refine_steps corrections
     // U += A_mixed^{-1} (F - A U) with the FP64 27-point residual (Section 3.1 operator)
-    double* R = reinterpret_cast<double*>(ws + off_R(p, nrhs));
+    // r is computed in FP64 and stored in FP32: it only feeds an FP32 correction solve,
+    // whose own rounding is larger; the last residual (the convergence check) is a norm only
+    float* R = reinterpret_cast<float*>(ws + off_R(p, nrhs));
     if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
     if (norm_pass(F, (long long)n3(p) * nrhs, reinterpret_cast<double*>(p->dstats) + 2, s) != hipSuccess)
       return CS3D_E_DEVICE;
     if (transform_solve<float>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
     for (int it = 0; it <= p->d.refine_steps; ++it) {
+      const bool last = it == p->d.refine_steps;
       if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
-      if (residual_pass(p, pd, F, u, R, nrhs, 3 + it, s) != hipSuccess) return CS3D_E_DEVICE;
-      if (it == p->d.refine_steps) break;
+      if (residual_pass<float>(p, pd, F, u, last ? nullptr : R, nrhs, 3 + it, s) != hipSuccess)
+        return CS3D_E_DEVICE;
+      if (last) break;
       ProbDev pc = pd;
-      pc.F = R;
+      pc.F = reinterpret_cast<const double*>(R);
+      pc.f32_input = 1;
       pc.accumulate = 1;
       if (transform_solve<float>(p, pc, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
     }
@@ -948,7 +968,7 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   // F (with the lift) goes into r, then r = F - A U in place
   const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
   if (!assembled && run_rhs(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
-  return residual_pass(p, pd, assembled ? dev_f : (const double*)dev_r, dev_u, dev_r, nrhs, -1, s) == hipSuccess
+  return residual_pass<double>(p, pd, assembled ? dev_f : (const double*)dev_r, dev_u, dev_r, nrhs, -1, s) == hipSuccess
              ? CS3D_OK
              : CS3D_E_DEVICE;
 }

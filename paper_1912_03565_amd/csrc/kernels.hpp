@@ -25,7 +25,10 @@ namespace cs3d {
 
 enum SchemeId : int { kHelm2 = 2, kHelm4 = 4, kHelm6 = 6, kCd4 = 14, kWeights = 99 };
 
-constexpr int kTileJ = 8;     // y-lines per K1/K4 workgroup (one wavefront each)
+#ifndef CS3D_TILEJ
+#define CS3D_TILEJ 8
+#endif
+constexpr int kTileJ = CS3D_TILEJ;  // y-lines per K1/K4 workgroup (one wavefront each)
 constexpr int kBlockY = 256;  // threads per K2/K3 workgroup
 
 struct ProbDev {
@@ -61,6 +64,7 @@ struct ProbDev {
   double* C;           // [nz][nx][ldy]   c' of the tridiagonal LU
   unsigned long long* stats;  // [0] = bits of min |pivot|, [1] = count of bad pivots
   int accumulate;      // K4: u += result (refinement corrections) instead of u = result
+  int f32_input;       // K1: F holds FP32 values (the residuals of the mixed path)
   int zchunk;          // planes per workgroup of the z-marching passes (K0, residual)
   // complex k (absorbing media): imaginary parts; a complex right-hand side q occupies the
   // real slots 2q (real part) and 2q+1 (imaginary part) of f, F, u, G and the z-face data
@@ -120,10 +124,12 @@ __host__ __device__ constexpr int tw_bytes() {
   return M ? tw_entries<M>() * (int)sizeof(cx<T>) : 0;
 }
 
-// row stride (>= nx + 1, = 4 mod 32) of the K1/K4 transpose tile: the transposed
-// accesses (8 rows x 4 columns per half-wave) then hit 32 distinct bank pairs, and a
-// row starts 16-byte aligned
-__host__ __device__ constexpr int tile_stride(int nx) { return ((nx + 1 - 4 + 31) / 32) * 32 + 4; }
+// row stride (>= nx + 1, = 32 / kTileJ mod 32) of the K1/K4 transpose tile: the transposed
+// accesses (kTileJ rows x 32 / kTileJ columns per half-wave) then hit 32 distinct bank
+// pairs, and a row starts 16-byte aligned
+__host__ __device__ constexpr int tile_stride(int nx) {
+  return ((nx + 1 - 32 / kTileJ + 31) / 32) * 32 + 32 / kTileJ;
+}
 
 // ---------------------------------------------------------------------------
 // Hide a value from loop-invariant code motion (an empty asm statement that claims to
@@ -560,7 +566,8 @@ __device__ __forceinline__ XTile decode_xtile(const ProbDev& p, int t, int w) {
   return x;
 }
 
-template <typename T, int MX, int KIND = kDst>
+// TI: element type of the input p.F (FP32 for the residuals of the mixed path)
+template <typename T, int MX, int KIND = kDst, typename TI = double>
 __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -571,14 +578,14 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
   cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
-  double pre[kNV];
+  TI pre[kNV];
   auto fetch = [&](int t) {
     const XTile x = decode_xtile(p, t, w);
     const int ln = opaque(lane);
-    const double* Fr =
-        p.F + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1)) + ln;
+    const TI* Fr = reinterpret_cast<const TI*>(p.F) + x.r * p.u_stride +
+                   (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1)) + ln;
 #pragma unroll
-    for (int k = 0; k < kNV; ++k) pre[k] = (x.active && ln + 64 * k < p.nx) ? Fr[64 * k] : 0.0;
+    for (int k = 0; k < kNV; ++k) pre[k] = (x.active && ln + 64 * k < p.nx) ? Fr[64 * k] : (TI)0;
   };
   int t = xcd_order(blockIdx.x, gridDim.x);
   if (t < ntiles) fetch(t);
@@ -1283,8 +1290,11 @@ constexpr int kQTX = 64, kQTY = 16, kQThreads = 512, kQRows = kQTY / (kQThreads 
 constexpr int kQX = kQTX + 2, kQY = kQTY + 2;
 constexpr int kQLoads = (kQX * kQY + kQThreads - 1) / kQThreads;
 
+// TR: element type of r (FP32 where it only feeds an FP32 correction solve); STORE = false
+// computes the norm alone (the last residual of a mixed solve)
+template <typename TR, bool STORE>
 __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double* __restrict__ Fi,
-                                                        const double* __restrict__ U, double* __restrict__ R,
+                                                        const double* __restrict__ U, TR* __restrict__ R,
                                                         double* acc) {
   __shared__ double win[3][kQX * kQY];
   __shared__ double part[kQThreads / 64];
@@ -1367,7 +1377,7 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
       }
       const long long idx = r * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
       const double rr = fl[k] - au;
-      R[idx] = rr;
+      if constexpr (STORE) R[idx] = (TR)rr;
       ss += rr * rr;
     }
   };
