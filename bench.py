@@ -54,7 +54,7 @@ def stage_bytes(nx, ny, nz, nrhs, elem=8):
 
 STAGE_NAMES = ["k_rhs (RHS operator + lift)", "k_fwd_x (x-DST)", "k_fwd_y (y-DST + forward elimination)",
                "k_back_y (back substitution + inverse y-DST)", "k_inv_x (inverse x-DST)",
-               "k_residual + k_sumsq (FP64 residual)"]
+               "k_residual (FP64 residual)"]
 STAGE_KEYS = ["k_rhs", "k_fwd_x", "k_fwd_y", "k_back_y", "k_inv_x", "k_residual"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp64_helm6_1023cubed_x4rhs.json")
 

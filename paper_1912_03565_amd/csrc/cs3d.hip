@@ -855,21 +855,21 @@ static hipError_t run_rhs_cx(const cs3d_plan p, const ProbDev& pd, int nrhs, hip
   return hipGetLastError();
 }
 
-static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s);
 
 // r = F - A U (FP64 arithmetic) and its squared norm into stats word `slot` (slot < 0: no
-// norm); r is stored as TR, or not at all when R is null
+// norm); r is stored as TR, or not at all when R is null; slotF >= 0 also sums ||F||^2 there
 template <typename TR>
 static hipError_t residual_pass(cs3d_plan p, const ProbDev& pd, const double* F, const double* U, TR* R,
-                                int nrhs, int slot, hipStream_t s) {
+                                int nrhs, int slot, hipStream_t s, int slotF = -1) {
   const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kQTX - 1) / kQTX, (p->d.ny + kQTY - 1) / kQTY, nzc * nrhs);
   if (grid.z > 65535u || grid.y > 65535u) return hipErrorInvalidValue;
   double* acc = slot >= 0 ? reinterpret_cast<double*>(p->dstats) + slot : nullptr;
+  double* accF = (slot >= 0 && slotF >= 0) ? reinterpret_cast<double*>(p->dstats) + slotF : nullptr;
   if (R) {
-    hipLaunchKernelGGL((k_residual<TR, true>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
+    hipLaunchKernelGGL((k_residual<TR, true>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc, accF);
   } else {
-    hipLaunchKernelGGL((k_residual<TR, false>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc);
+    hipLaunchKernelGGL((k_residual<TR, false>), grid, dim3(kQThreads), 0, s, pd, F, U, R, acc, accF);
   }
   return hipGetLastError();
 }
@@ -913,15 +913,13 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
     // U += A_mixed^{-1} (F - A U) with the FP64 27-point residual (Section 3.1 operator)
     // r is computed in FP64 and stored in FP32: it only feeds an FP32 correction solve,
     // whose own rounding is larger; the last residual (the convergence check) is a norm only
+    // ||F||^2 (stats word 2, the scale of the residual history) comes with the first residual
     float* R = reinterpret_cast<float*>(ws + off_R(p, nrhs));
-    if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
-    if (norm_pass(F, (long long)n3(p) * nrhs, reinterpret_cast<double*>(p->dstats) + 2, s) != hipSuccess)
-      return CS3D_E_DEVICE;
     if (transform_solve<float>(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
     for (int it = 0; it <= p->d.refine_steps; ++it) {
       const bool last = it == p->d.refine_steps;
       if (mark(p, 5, s) != hipSuccess) return CS3D_E_DEVICE;
-      if (residual_pass<float>(p, pd, F, u, last ? nullptr : R, nrhs, 3 + it, s) != hipSuccess)
+      if (residual_pass<float>(p, pd, F, u, last ? nullptr : R, nrhs, 3 + it, s, it == 0 ? 2 : -1) != hipSuccess)
         return CS3D_E_DEVICE;
       if (last) break;
       ProbDev pc = pd;
@@ -936,14 +934,6 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   if (hipEventRecord(p->ev1, s) != hipSuccess) return CS3D_E_DEVICE;
   p->timed = true;
   return CS3D_OK;
-}
-
-static hipError_t norm_pass(const double* x, long long n, double* acc, hipStream_t s) {
-  long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)blocks), dim3(256), 0, s, x, n, acc);
-  return hipGetLastError();
 }
 
 extern "C" cs3d_status cs3d_solve(cs3d_plan p, int nrhs, const double* dev_f, const double* dev_g_lo,

@@ -1292,12 +1292,13 @@ constexpr int kQLoads = (kQX * kQY + kQThreads - 1) / kQThreads;
 
 // TR: element type of r (FP32 where it only feeds an FP32 correction solve); STORE = false
 // computes the norm alone (the last residual of a mixed solve)
+// accF (may be null): also accumulates ||F||^2 over the same points
 template <typename TR, bool STORE>
 __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double* __restrict__ Fi,
                                                         const double* __restrict__ U, TR* __restrict__ R,
-                                                        double* acc) {
+                                                        double* acc, double* accF) {
   __shared__ double win[3][kQX * kQY];
-  __shared__ double part[kQThreads / 64];
+  __shared__ double part[kQThreads / 64], partF[kQThreads / 64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
@@ -1339,7 +1340,7 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
   fetch(pa, lb + 1);
   fetch(pb, lb + 2);
   const int i = x0 + tx;
-  double ss = 0.0;
+  double ss = 0.0, sf = 0.0;
   // F of the rows a thread owns, fetched two planes ahead like U; the weights come through
   // scalar loads, so no wait in the stencil phase holds up the prefetched planes
   double fA[kQRows], fB[kQRows];
@@ -1379,6 +1380,7 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
       const double rr = fl[k] - au;
       if constexpr (STORE) R[idx] = (TR)rr;
       ss += rr * rr;
+      sf += fl[k] * fl[k];
     }
   };
   for (int l = lb; l <= le; l += 2) {
@@ -1397,13 +1399,23 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
       __syncthreads();
     }
   }
-  for (int off2 = 32; off2 > 0; off2 >>= 1) ss += __shfl_xor(ss, off2, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = ss;
+  for (int off2 = 32; off2 > 0; off2 >>= 1) {
+    ss += __shfl_xor(ss, off2, 64);
+    sf += __shfl_xor(sf, off2, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[threadIdx.x >> 6] = ss;
+    partF[threadIdx.x >> 6] = sf;
+  }
   __syncthreads();
   if (threadIdx.x == 0 && acc) {
-    double t = 0.0;
-    for (int q = 0; q < kQThreads / 64; ++q) t += part[q];
+    double t = 0.0, tf = 0.0;
+    for (int q = 0; q < kQThreads / 64; ++q) {
+      t += part[q];
+      tf += partF[q];
+    }
     atomicAdd(acc, t);
+    if (accF) atomicAdd(accF, tf);
   }
 }
 
@@ -1417,18 +1429,6 @@ __global__ void k_stats_reset(unsigned long long* s) {
     s[1] = 0ull;
   }
   if (threadIdx.x >= 2 && threadIdx.x < kStatsWords) s[threadIdx.x] = 0ull;  // +0.0
-}
-
-// acc += sum of squares of x[0..n) (one FP64 atomic per workgroup)
-__global__ void __launch_bounds__(256) k_sumsq(const double* __restrict__ x, long long n, double* acc) {
-  __shared__ double part[4];
-  double s = 0.0;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
-    s += x[e] * x[e];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(acc, part[0] + part[1] + part[2] + part[3]);
 }
 
 }  // namespace cs3d
