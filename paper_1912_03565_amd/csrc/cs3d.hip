@@ -693,7 +693,7 @@ static hipError_t run_y_back(const cs3d_plan p, const ProbDev& pd, int nrhs, hip
 
 static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   if (p->neu) {
-    const dim3 grid((p->d.nx * p->d.ny + 255) / 256, p->d.nz, nrhs);
+    const dim3 grid((p->d.nx * p->d.ny + 255) / 256, (p->d.nz + kSidesChunk - 1) / kSidesChunk, nrhs);
     if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rhs_sides, grid, dim3(256), 0, s, pd);
     return hipGetLastError();

@@ -19,6 +19,8 @@
 // the same routine and the orthonormal V of Section 3.6 is recovered by the single
 // final scale.
 #pragma once
+#include <type_traits>
+
 #include "wave_dst.hpp"
 
 namespace cs3d {
@@ -472,72 +474,111 @@ __global__ void __launch_bounds__(256) k_rhs_faces(ProbDev p, int axis) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int mirror(int i, int n) { return i < 0 ? -i : (i >= n ? 2 * (n - 1) - i : i); }
 
+// Each thread owns a node (i, j) and marches over a chunk of kSidesChunk planes, keeping the
+// 13-point neighbourhoods (centre, the 4 face and 4 edge neighbours, the 4 at distance 2) of
+// the planes l-2..l+2 in a ring of registers: one new neighbourhood is loaded per plane.
+// grid: (ceil(nx ny / 256), ceil(nz / kSidesChunk), right-hand sides)
+constexpr int kSidesChunk = 60;  // a multiple of the ring's 5, so ring slots are compile-time
+
 __global__ void __launch_bounds__(256) k_rhs_sides(ProbDev p) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= p.nx * p.ny) return;
-  const int i = e % p.nx, j = e / p.nx, l = 1 + blockIdx.y, r = blockIdx.z;
-  const int nx = p.nx, ny = p.ny;
+  const int i = e % p.nx, j = e / p.nx, r = blockIdx.z;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int lb = 1 + blockIdx.y * kSidesChunk, le = min(nz, lb + kSidesChunk - 1);
   const double* f = p.f + r * p.f_stride;
-  auto at = [&](int di, int dj, int dl) -> double {
-    return f[mirror(i + di, nx) + (long long)nx * (mirror(j + dj, ny) + (long long)ny * (l + dl))];
+  const long long P = (long long)nx * ny;
+  // mirrored in-plane offsets, slot order: c, x-1, x+1, y-1, y+1, (x-1,y-1), (x+1,y-1),
+  // (x-1,y+1), (x+1,y+1), x-2, x+2, y-2, y+2
+  constexpr int DX[13] = {0, -1, 1, 0, 0, -1, 1, -1, 1, -2, 2, 0, 0};
+  constexpr int DY[13] = {0, 0, 0, -1, 1, -1, -1, 1, 1, 0, 0, -2, 2};
+  int off[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) off[k] = mirror(i + DX[k], nx) + nx * mirror(j + DY[k], ny);
+  double ring[5][13];
+  auto load = [&](double(&v)[13], int q) {  // planes outside 0..nz+1 are never used
+    const double* fq = f + P * (q < 0 ? 0 : (q > nz + 1 ? nz + 1 : q));
+#pragma unroll
+    for (int k = 0; k < 13; ++k) v[k] = fq[off[k]];
   };
+  auto centre = [&](int q) { return f[P * q + off[0]]; };
   const double hz2 = p.hz * p.hz;
-  const double f0 = at(0, 0, 0);
-  double F;
-  if (p.scheme == kHelm2) {
-    F = hz2 * f0;
-  } else {
-    const double d2x = at(-1, 0, 0) - 2.0 * f0 + at(1, 0, 0);
-    const double d2y = at(0, -1, 0) - 2.0 * f0 + at(0, 1, 0);
-    const double d2z = at(0, 0, -1) - 2.0 * f0 + at(0, 0, 1);
-    if (p.scheme == kHelm4) {
-      F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
-    } else if (p.scheme == kCd4) {
-      const double d1z = 0.5 * (at(0, 0, 1) - at(0, 0, -1));
-      F = hz2 * (f0 + d2x * (1.0 / 12.0) + d2y * (1.0 / 12.0) + (p.hz * p.gamma * d1z + d2z) * (1.0 / 12.0));
+  // plane l sits in ring slot S = l mod 5 (lb = 1 mod 5)
+  auto plane = [&](int l, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const double(&c)[13] = ring[S];
+    const double(&m1)[13] = ring[(S + 4) % 5];
+    const double(&p1)[13] = ring[(S + 1) % 5];
+    const double f0 = c[0];
+    double F;
+    if (p.scheme == kHelm2) {
+      F = hz2 * f0;
     } else {
-      // 6th order: f + sum d2/12 - sum d4/240 + sum d2d2/90 - h^2 k^2 f/20 + h^3 (k^2)_z d1z/60
-      const double h = p.hz, kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
-      const double d4x = at(-2, 0, 0) - 4.0 * (at(-1, 0, 0) + at(1, 0, 0)) + 6.0 * f0 + at(2, 0, 0);
-      const double d4y = at(0, -2, 0) - 4.0 * (at(0, -1, 0) + at(0, 1, 0)) + 6.0 * f0 + at(0, 2, 0);
-      double d4z;
-      if (l == 1) {
-        d4z = 2.0 * at(0, 0, -1) - 9.0 * f0 + 16.0 * at(0, 0, 1) - 14.0 * at(0, 0, 2) + 6.0 * at(0, 0, 3) -
-              at(0, 0, 4);
-      } else if (l == p.nz) {
-        d4z = 2.0 * at(0, 0, 1) - 9.0 * f0 + 16.0 * at(0, 0, -1) - 14.0 * at(0, 0, -2) + 6.0 * at(0, 0, -3) -
-              at(0, 0, -4);
+      const double d2x = c[1] - 2.0 * f0 + c[2];
+      const double d2y = c[3] - 2.0 * f0 + c[4];
+      const double d2z = m1[0] - 2.0 * f0 + p1[0];
+      if (p.scheme == kHelm4) {
+        F = hz2 * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0));
+      } else if (p.scheme == kCd4) {
+        const double d1z = 0.5 * (p1[0] - m1[0]);
+        F = hz2 * (f0 + d2x * (1.0 / 12.0) + d2y * (1.0 / 12.0) + (p.hz * p.gamma * d1z + d2z) * (1.0 / 12.0));
       } else {
-        d4z = at(0, 0, -2) - 4.0 * (at(0, 0, -1) + at(0, 0, 1)) + 6.0 * f0 + at(0, 0, 2);
+        // 6th order: f + sum d2/12 - sum d4/240 + sum d2d2/90 - h^2 k^2 f/20 + h^3 (k^2)_z d1z/60
+        const double h = p.hz, kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
+        const double d4x = c[9] - 4.0 * (c[1] + c[2]) + 6.0 * f0 + c[10];
+        const double d4y = c[11] - 4.0 * (c[3] + c[4]) + 6.0 * f0 + c[12];
+        double d4z;
+        if (l == 1) {
+          d4z = 2.0 * m1[0] - 9.0 * f0 + 16.0 * p1[0] - 14.0 * ring[(S + 2) % 5][0] + 6.0 * centre(l + 3) -
+                centre(l + 4);
+        } else if (l == nz) {
+          d4z = 2.0 * p1[0] - 9.0 * f0 + 16.0 * m1[0] - 14.0 * ring[(S + 3) % 5][0] + 6.0 * centre(l - 3) -
+                centre(l - 4);
+        } else {
+          d4z = ring[(S + 3) % 5][0] - 4.0 * (m1[0] + p1[0]) + 6.0 * f0 + ring[(S + 2) % 5][0];
+        }
+        // products of second differences over the three coordinate planes (the sums of the
+        // 3 x 3 weights (1, -2, 1) x (1, -2, 1), taken row by row)
+        const double sxy = (c[5] - 2.0 * c[3] + c[6]) - 2.0 * (c[1] - 2.0 * f0 + c[2]) + (c[7] - 2.0 * c[4] + c[8]);
+        const double sxz = (m1[1] - 2.0 * m1[0] + m1[2]) - 2.0 * (c[1] - 2.0 * f0 + c[2]) + (p1[1] - 2.0 * p1[0] + p1[2]);
+        const double syz = (m1[3] - 2.0 * m1[0] + m1[4]) - 2.0 * (c[3] - 2.0 * f0 + c[4]) + (p1[3] - 2.0 * p1[0] + p1[4]);
+        const double sx = sxy + sxz + syz;
+        const double d1z = 0.5 * (p1[0] - m1[0]);
+        F = h * h * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - (d4x + d4y + d4z) * (1.0 / 240.0) + sx * (1.0 / 90.0) -
+                     h * h * kl * f0 * (1.0 / 20.0) + h * h * h * kzl * d1z * (1.0 / 60.0));
       }
-      // products of second differences over the three coordinate planes
-      auto d2d2 = [&](int ax, int bx) -> double {
-        double acc = 0.0;
-        for (int da = -1; da <= 1; ++da)
-          for (int db = -1; db <= 1; ++db) {
-            const double wa = da ? 1.0 : -2.0, wb = db ? 1.0 : -2.0;
-            int d[3] = {0, 0, 0};
-            d[ax] = da;
-            d[bx] = db;
-            acc += wa * wb * at(d[0], d[1], d[2]);
-          }
-        return acc;
-      };
-      const double sx = d2d2(0, 1) + d2d2(0, 2) + d2d2(1, 2);
-      const double d1z = 0.5 * (at(0, 0, 1) - at(0, 0, -1));
-      F = h * h * (f0 + (d2x + d2y + d2z) * (1.0 / 12.0) - (d4x + d4y + d4z) * (1.0 / 240.0) + sx * (1.0 / 90.0) -
-                   h * h * kl * f0 * (1.0 / 20.0) + h * h * h * kzl * d1z * (1.0 / 60.0));
     }
-  }
-  // lift of the z-face data (both faces when nz = 1)
-  auto plane9m = [&](const double* w, const double* P) -> double {
-    auto g = [&](int di, int dj) { return P[mirror(i + di, nx) + (long long)nx * mirror(j + dj, ny)]; };
-    return w[0] * (g(-1, -1) + g(1, -1) + g(-1, 1) + g(1, 1)) + w[1] * (g(-1, 0) + g(1, 0)) +
-           w[2] * (g(0, -1) + g(0, 1)) + w[3] * g(0, 0);
+    // lift of the z-face data (both faces when nz = 1)
+    auto plane9m = [&](const double* w, const double* Pl) -> double {
+      return w[0] * (Pl[off[5]] + Pl[off[6]] + Pl[off[7]] + Pl[off[8]]) + w[1] * (Pl[off[1]] + Pl[off[2]]) +
+             w[2] * (Pl[off[3]] + Pl[off[4]]) + w[3] * Pl[off[0]];
+    };
+    if (l == 1 && p.glo) F -= plane9m(p.W + 0, p.glo + r * p.g_stride);
+    if (l == nz && p.ghi) F -= plane9m(p.W + (nz - 1) * 12 + 8, p.ghi + r * p.g_stride);
+    p.u[r * p.u_stride + i + (long long)nx * (j + (long long)ny * (l - 1))] = F;
   };
-  if (l == 1 && p.glo) F -= plane9m(p.W + 0, p.glo + r * p.g_stride);
-  if (l == p.nz && p.ghi) F -= plane9m(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride);
-  p.u[r * p.u_stride + i + (long long)nx * (j + (long long)ny * (l - 1))] = F;
+  // planes lb-2 .. lb+1 into slots (lb-2) mod 5 .. (lb+1) mod 5 = 4, 0, 1, 2
+  load(ring[4], lb - 2);
+  load(ring[0], lb - 1);
+  load(ring[1], lb);
+  load(ring[2], lb + 1);
+  using std::integral_constant;
+  for (int l = lb; l <= le; l += 5) {
+    load(ring[3], l + 2);
+    plane(l, integral_constant<int, 1>{});
+    if (l + 1 > le) break;
+    load(ring[4], l + 3);
+    plane(l + 1, integral_constant<int, 2>{});
+    if (l + 2 > le) break;
+    load(ring[0], l + 4);
+    plane(l + 2, integral_constant<int, 3>{});
+    if (l + 3 > le) break;
+    load(ring[1], l + 5);
+    plane(l + 3, integral_constant<int, 4>{});
+    if (l + 4 > le) break;
+    load(ring[2], l + 6);
+    plane(l + 4, integral_constant<int, 0>{});
+  }
 }
 
 // ---------------------------------------------------------------------------
