@@ -78,12 +78,13 @@ __device__ __forceinline__ void dispatch_m(int M, Fn&& fn) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
   __shared__ double win[kRSlots][kSY * kSX];
+  __shared__ double kt[2 * kZMax];
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev& p = b.P[b.perm[k]];
     const int t = item - b.start[k];
     const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRY - 1) / kRY;
-    rhs_block<true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win);
+    rhs_block<true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win, kt);
   }
 }
 

@@ -850,7 +850,8 @@ static hipError_t transform_solve_c(cs3d_plan p, const ProbDev& pd, int nrhs, hi
 static hipError_t run_rhs_cx(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const bool h6 = p->d.scheme == CS3D_HELM6;
   if (!h6 && !pd.glo && !pd.ghi) return hipSuccess;
-  const dim3 grid((p->d.nx * p->d.ny + 255) / 256, h6 ? p->d.nz : (p->d.nz == 1 ? 1 : 2), nrhs);
+  const dim3 grid((p->d.nx * p->d.ny + 255) / 256,
+                  h6 ? (p->d.nz + kSidesChunk - 1) / kSidesChunk : (p->d.nz == 1 ? 1 : 2), nrhs);
   hipLaunchKernelGGL(k_rhs_cx, grid, dim3(256), 0, s, pd);
   return hipGetLastError();
 }

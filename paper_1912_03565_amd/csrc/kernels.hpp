@@ -153,12 +153,6 @@ __device__ __forceinline__ void settle(V (&a)[N]) {
   for (int k = 0; k < N; ++k) a[k] = opaque(a[k]);
 }
 
-// Read a plan table through the constant address space: the tables are never written
-// while a kernel runs, so uniform reads become scalar loads, which a wait for vector
-// memory operations (prefetched lines, stores) does not have to include.
-__device__ __forceinline__ double ctab(const double* t, int i) {
-  return ((const __attribute__((address_space(4))) double*)t)[i];
-}
 
 // ---------------------------------------------------------------------------
 // XCD-aware work order.  The 8 XCDs of the chip each have their own L2, and
@@ -235,6 +229,7 @@ __device__ __forceinline__ double face_corr(const ProbDev& p, int r, int i, int 
 }
 
 constexpr int kRThreads = 256;
+constexpr int kZMax = 512;  // largest z-chunk of the z-marching passes (the tuning range)
 constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread (4)
 constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
@@ -242,11 +237,19 @@ constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile 
 // corrections of the points on the faces of the box here (else k_rhs_faces does it)
 template <bool FACES>
 __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int zc, int r,
-                                          double (*win)[kSY * kSX]) {
+                                          double (*win)[kSY * kSX], double* kt) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = 1 + bx * kRX, y0 = 1 + by * kRY;
   const int lb = 1 + zc * p.zchunk;
   const int le = min(p.nz, lb + p.zchunk - 1);
+  // k^2 and (k^2)_z of the chunk's planes in LDS (kt[0..), kt[kZMax..)): read there, the
+  // per-plane samples cost no vector load, whose wait would also wait for the prefetched
+  // planes.  The barrier keeps a previous call's readers off the table.
+  __syncthreads();
+  for (int q = threadIdx.x; q <= le - lb; q += kRThreads) {
+    kt[q] = p.k2[lb + q];
+    kt[kZMax + q] = p.k2z[lb + q];
+  }
   const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
   const double* __restrict__ f = p.f + r * p.f_stride;
 
@@ -314,7 +317,7 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
     const double* P0 = win[slot(l)];
     const double* Pm = win[slot(l - 1)];
     const double* Pp = win[slot(l + 1)];
-    const double kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
+    const double kl = kt[l - lb], kzl = kt[kZMax + l - lb];
     // y-neighbours: own registers inside the thread's rows, LDS outside
     auto y0v = [&](int k, int d) -> double {
       const int kk = k + d;
@@ -427,10 +430,11 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
 // face corrections follow in k_rhs_faces
 __global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
   __shared__ double win[kRSlots][kSY * kSX];
+  __shared__ double kt[2 * kZMax];
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
-  rhs_block<false>(p, bx, by, bz % nzc, bz / nzc, win);
+  rhs_block<false>(p, bx, by, bz % nzc, bz / nzc, win, kt);
 }
 
 // Corrections of F on one pair of faces of the interior box (axis 0: x, 1: y, 2: z), one
@@ -524,7 +528,7 @@ __global__ void __launch_bounds__(256) k_rhs_sides(ProbDev p) {
         F = hz2 * (f0 + d2x * (1.0 / 12.0) + d2y * (1.0 / 12.0) + (p.hz * p.gamma * d1z + d2z) * (1.0 / 12.0));
       } else {
         // 6th order: f + sum d2/12 - sum d4/240 + sum d2d2/90 - h^2 k^2 f/20 + h^3 (k^2)_z d1z/60
-        const double h = p.hz, kl = ctab(p.k2, l), kzl = ctab(p.k2z, l);
+        const double h = p.hz, kl = p.k2[l], kzl = p.k2z[l];
         const double d4x = c[9] - 4.0 * (c[1] + c[2]) + 6.0 * f0 + c[10];
         const double d4y = c[11] - 4.0 * (c[3] + c[4]) + 6.0 * f0 + c[12];
         double d4z;
@@ -803,10 +807,10 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       settle(pre);  // the next line, fetched before the transform
       if (r == 0) {
         // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
-        const int lc = (l - 1) * 12;
-        const double bm = ctab(p.LC, lc + 0) + ctn * ctab(p.LC, lc + 1), am = ctab(p.LC, lc + 2) + ctab(p.LC, lc + 3) * ctn;
-        const double b0 = ctab(p.LC, lc + 4) + ctn * ctab(p.LC, lc + 5), a0 = ctab(p.LC, lc + 6) + ctab(p.LC, lc + 7) * ctn;
-        const double bp = ctab(p.LC, lc + 8) + ctn * ctab(p.LC, lc + 9), ap = ctab(p.LC, lc + 10) + ctab(p.LC, lc + 11) * ctn;
+        const double* Ll = p.LC + (l - 1) * 12;
+        const double bm = Ll[0] + ctn * Ll[1], am = Ll[2] + Ll[3] * ctn;
+        const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
+        const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
         double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
         if constexpr (kHoistS) {
 #pragma unroll
@@ -1086,35 +1090,52 @@ __global__ void __launch_bounds__(256) k_rhs_cx(ProbDev p) {
   if (e >= p.nx * p.ny) return;
   const int i = 1 + e % p.nx, j = 1 + e / p.nx;
   const bool h6 = p.scheme == kHelm6;
-  const int l = h6 ? 1 + (int)blockIdx.y : (blockIdx.y == 0 ? 1 : p.nz);
   const int q = blockIdx.z;
   const long long sy = p.nx + 2, sz = (long long)(p.nx + 2) * (p.ny + 2);
-  const long long idx = (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
-  double dre = 0.0, dim = 0.0;  // corrections of Re F and Im F
-  if (h6 && p.f) {
-    const double* fr = p.f + (2 * q) * p.f_stride + i + sy * j + sz * l;
-    const double* fi = fr + p.f_stride;
-    const double h = p.hz, hz2 = h * h;
-    const double ki = p.k2i[l], kzi = p.k2zi[l];
-    // -(h^2/20) k^2 f + (h^3/120) (k^2)_z (f_{l+1} - f_{l-1}), imaginary-part products
-    dre = hz2 * (h * h * ki * fi[0] * (1.0 / 20.0) - h * h * h * kzi * (fi[sz] - fi[-sz]) * (1.0 / 120.0));
-    dim = hz2 * (-h * h * ki * fr[0] * (1.0 / 20.0) + h * h * h * kzi * (fr[sz] - fr[-sz]) * (1.0 / 120.0));
+  // 6th order: a z-march over a chunk of planes with f_{l-1}, f_l, f_{l+1} of both parts
+  // in registers; otherwise the two lift planes (blockIdx.y = 0: plane 1, 1: plane nz)
+  const int lb = h6 ? 1 + (int)blockIdx.y * kSidesChunk : (blockIdx.y == 0 ? 1 : p.nz);
+  const int le = h6 ? min(p.nz, lb + kSidesChunk - 1) : lb;
+  const double* fr = (h6 && p.f) ? p.f + (2 * q) * p.f_stride + i + sy * j : nullptr;
+  const double* fi = fr ? fr + p.f_stride : nullptr;
+  double rm = 0.0, r0 = 0.0, rp = 0.0, im = 0.0, i0 = 0.0, ip = 0.0;
+  if (fr) {
+    rm = fr[sz * (lb - 1)];
+    r0 = fr[sz * lb];
+    im = fi[sz * (lb - 1)];
+    i0 = fi[sz * lb];
   }
-  // lift: F -= W g with complex W and g; the real parts were lifted per slot
-  if (l == 1 && p.glo) {
-    const double* gr = p.glo + (2 * q) * p.g_stride;
-    dre += plane9(p.Wi + 0, gr + p.g_stride, p.nx, i, j);
-    dim -= plane9(p.Wi + 0, gr, p.nx, i, j);
+  for (int l = lb; l <= le; ++l) {
+    double dre = 0.0, dim = 0.0;  // corrections of Re F and Im F
+    if (fr) {
+      rp = fr[sz * (l + 1)];
+      ip = fi[sz * (l + 1)];
+      const double h = p.hz, hz2 = h * h;
+      const double ki = p.k2i[l], kzi = p.k2zi[l];
+      // -(h^2/20) k^2 f + (h^3/120) (k^2)_z (f_{l+1} - f_{l-1}), imaginary-part products
+      dre = hz2 * (h * h * ki * i0 * (1.0 / 20.0) - h * h * h * kzi * (ip - im) * (1.0 / 120.0));
+      dim = hz2 * (-h * h * ki * r0 * (1.0 / 20.0) + h * h * h * kzi * (rp - rm) * (1.0 / 120.0));
+    }
+    // lift: F -= W g with complex W and g; the real parts were lifted per slot
+    if (l == 1 && p.glo) {
+      const double* gr = p.glo + (2 * q) * p.g_stride;
+      dre += plane9(p.Wi + 0, gr + p.g_stride, p.nx, i, j);
+      dim -= plane9(p.Wi + 0, gr, p.nx, i, j);
+    }
+    if (l == p.nz && p.ghi) {
+      const double* gr = p.ghi + (2 * q) * p.g_stride;
+      const double* w = p.Wi + (p.nz - 1) * 12 + 8;
+      dre += plane9(w, gr + p.g_stride, p.nx, i, j);
+      dim -= plane9(w, gr, p.nx, i, j);
+    }
+    double* u = p.u + (2 * q) * p.u_stride + (i - 1) + (long long)p.nx * ((j - 1) + (long long)p.ny * (l - 1));
+    u[0] += dre;
+    u[p.u_stride] += dim;
+    rm = r0;
+    r0 = rp;
+    im = i0;
+    i0 = ip;
   }
-  if (l == p.nz && p.ghi) {
-    const double* gr = p.ghi + (2 * q) * p.g_stride;
-    const double* w = p.Wi + (p.nz - 1) * 12 + 8;
-    dre += plane9(w, gr + p.g_stride, p.nx, i, j);
-    dim -= plane9(w, gr, p.nx, i, j);
-  }
-  double* u = p.u + (2 * q) * p.u_stride + idx;
-  u[0] += dre;
-  u[p.u_stride] += dim;
 }
 
 __device__ __forceinline__ void record_pivot_c(double pr, double pi, double& minpiv, unsigned& bad) {
@@ -1160,6 +1181,9 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
 #pragma unroll
     for (int s = 0; s < C::NLD; ++s) pre[s] = (active && tl + C::LANES * s <= p.ny) ? src[C::LANES * s] : 0.0;
   };
+  // the plane's coefficients Z, B, C, A (real parts, then imaginary), loaded just before
+  // the second line's prefetch and settled with it: the elimination then waits for no load
+  double Lc[24];
   fetch(1, 0);
   settle(pre);
   for (int l = 1; l <= p.nz; ++l) {
@@ -1171,22 +1195,26 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
         if (e <= p.ny) buf[e] = pre[s];
       }
       line_sync<WPL>();
-      if (part == 0) fetch(l, 1);
-      else if (l < p.nz) fetch(l + 1, 0);
+      if (part == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          Lc[k] = p.LC[(l - 1) * 12 + k];
+          Lc[12 + k] = p.LCi[(l - 1) * 12 + k];
+        }
+        fetch(l, 1);
+      } else if (l < p.nz) {
+        fetch(l + 1, 0);
+      }
       double out[NS];
       line_dst<double, MY, WPL>(buf, p.ny, out, tl, tab, p.siny);
       settle(pre);  // the next line, fetched before the transform
       if (part == 0) {
+        settle(Lc);
 #pragma unroll
         for (int s = 0; s < NS; ++s) orr[s] = out[s];
       } else if (active) {
-        // plan tables through scalar loads (see ctab)
-        double Lr[12], Li[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          Lr[k] = ctab(p.LC, (l - 1) * 12 + k);
-          Li[k] = ctab(p.LCi, (l - 1) * 12 + k);
-        }
+        const double* Lr = Lc;
+        const double* Li = Lc + 12;
         double* Cr = p.C + (long long)(l - 1) * lstride + nbase;
         double* Cim = p.Ci + (long long)(l - 1) * lstride + nbase;
         double* d0 = G0 + (long long)(l - 1) * lstride + nbase;
@@ -1328,6 +1356,7 @@ __global__ void __launch_bounds__(kBlockY) k_back_y_c(ProbDev p) {
 // three-plane window of U (halo 1) in LDS and two planes in flight in registers.
 // ---------------------------------------------------------------------------
 constexpr int kQTX = 64, kQTY = 16, kQThreads = 512, kQRows = kQTY / (kQThreads / 64);
+constexpr int kQWPlanes = 64;  // planes per refill of the residual's weight table (even)
 constexpr int kQX = kQTX + 2, kQY = kQTY + 2;
 constexpr int kQLoads = (kQX * kQY + kQThreads - 1) / kQThreads;
 
@@ -1340,6 +1369,8 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
                                                         double* acc, double* accF) {
   __shared__ double win[3][kQX * kQY];
   __shared__ double part[kQThreads / 64], partF[kQThreads / 64];
+  // the weights of kQWPlanes planes at a time, in LDS (see kt in rhs_block)
+  __shared__ double wt[12 * kQWPlanes];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
@@ -1382,8 +1413,8 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
   fetch(pb, lb + 2);
   const int i = x0 + tx;
   double ss = 0.0, sf = 0.0;
-  // F of the rows a thread owns, fetched two planes ahead like U; the weights come through
-  // scalar loads, so no wait in the stencil phase holds up the prefetched planes
+  // F of the rows a thread owns, fetched two planes ahead like U; the weights are read from
+  // LDS, so no wait in the stencil phase holds up the prefetched planes
   double fA[kQRows], fB[kQRows];
   auto fetchF = [&](double(&dst)[kQRows], int q) {
 #pragma unroll
@@ -1402,7 +1433,7 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
     const double* Pp = win[(l + 1) % 3];
     double w[12];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) w[q] = ctab(p.W, (l - 1) * 12 + q);
+    for (int q = 0; q < 12; ++q) w[q] = wt[((l - lb) % kQWPlanes) * 12 + q];
 #pragma unroll
     for (int k = 0; k < kQRows; ++k) {
       const int yl = ty * kQRows + k, j = y0 + yl;
@@ -1425,6 +1456,10 @@ __global__ void __launch_bounds__(kQThreads) k_residual(ProbDev p, const double*
     }
   };
   for (int l = lb; l <= le; l += 2) {
+    if ((l - lb) % kQWPlanes == 0) {  // every reader of the previous block passed a barrier
+      const int n = 12 * min(kQWPlanes, le - l + 1);
+      for (int q = threadIdx.x; q < n; q += kQThreads) wt[q] = p.W[(l - 1) * 12 + q];
+    }
     stash(pa, l + 1);
     __syncthreads();
     if (l + 2 <= le) fetch(pa, l + 3);
