@@ -1,0 +1,104 @@
+"""Plans opened one after another on the same shape, each closed before the next opens.
+
+The device allocator hands a new plan the addresses its predecessor freed, so every table
+read by a kernel (the k^2 samples of the right-hand side pass, the stencil weights of the
+residual, the modal coefficients of the y passes) then holds new values at an address
+that held the previous plan's.  Each solve must follow its own k(z): the FP64, mixed,
+complex and Neumann paths are checked against the oracle for three different media in
+turn, twice over.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+SHAPE = (63, 31, 17)
+
+PROFILES = [
+    WL.problems.KProfile(lambda z: 6.0 + 2.0 * np.sin(3.0 * z), lambda z: 6.0 * np.cos(3.0 * z),
+                         lambda z: -18.0 * np.sin(3.0 * z)),
+    WL.problems.KProfile(lambda z: 20.0 + 5.0 * np.sin(z), lambda z: 5.0 * np.cos(z),
+                         lambda z: -5.0 * np.sin(z)),
+    WL.problems.KProfile(lambda z: 3.0 + np.cos(2.0 * z), lambda z: -2.0 * np.sin(2.0 * z),
+                         lambda z: -4.0 * np.cos(2.0 * z)),
+]
+CPROFILES = [
+    WL.problems.K_ABSORB,
+    WL.problems.KProfile(lambda z: (15.0 + z) + 2j * (1.0 + z), lambda z: 1.0 + 2j,
+                         lambda z: 0.0 * z),
+]
+
+
+@pytest.fixture(scope="module")
+def cs3d():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1912_03565_amd as m
+    return m
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle(p, sides="dirichlet", dtype=np.longdouble):
+    gl = None if p.g_lo is None else p.g_lo[0].numpy()
+    gh = None if p.g_hi is None else p.g_hi[0].numpy()
+    return O.solve(p.scheme, p.f[0].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz, p.gamma,
+                   gl, gh, dtype=dtype, sides=sides).U
+
+
+def _bar(p, ref, tol, sides="dirichlet"):
+    """tol, or four times the plain FP64 oracle's own error where the medium makes that
+    larger (the parity suite's bar)."""
+    return max(tol, 4.0 * _rel(_oracle(p, sides, np.float64), ref))
+
+
+def _dev(t, cplx):
+    """To the device; complex data as planes of real, then imaginary parts."""
+    if t is None:
+        return None
+    return (torch.stack([t.real, t.imag], dim=1).contiguous() if cplx else t).to(DEV)
+
+
+def _solve(cs3d, p, **kw):
+    plan = cs3d.plan_for_problem(p, device=DEV, **kw)
+    c = plan.complex
+    u = plan.solve(_dev(p.f, c), _dev(p.g_lo, c), _dev(p.g_hi, c)).cpu().numpy()
+    plan.close()
+    return u[0, 0] + 1j * u[0, 1] if c else u[0]
+
+
+@pytest.mark.parametrize("path", ["fp64", "mixed", "neumann"])
+def test_real_plans_in_turn_follow_their_own_medium(cs3d, path):
+    nx, ny, nz = SHAPE
+    for rep in range(2):
+        for i, prof in enumerate(PROFILES):
+            if path == "neumann":
+                p = WL.neumann_noise_problem(nx, ny, nz, "helm6", seed=300 + i)
+                p.k2, p.k2_z, p.k2_zz = WL.problems._zsamples(nz, p.hz, prof)
+                kw, sides = {}, "neumann"
+            else:
+                p = WL.noise_problem(nx, ny, nz, "helm6", seed=300 + i, prof=prof)
+                kw = {"precision": "mixed", "refine_steps": 2} if path == "mixed" else {}
+                sides = "dirichlet"
+            print(f"case {path} medium {i} pass {rep}", flush=True)
+            ref = _oracle(p, sides)
+            err = _rel(_solve(cs3d, p, **kw), ref)
+            assert err < _bar(p, ref, 1e-10 if path == "mixed" else 1e-12, sides), (path, rep, i, err)
+
+
+def test_complex_plans_in_turn_follow_their_own_medium(cs3d):
+    nx, ny, nz = SHAPE
+    for rep in range(2):
+        for i, prof in enumerate(CPROFILES):
+            p = WL.complex_noise_problem(nx, ny, nz, "helm6", seed=310 + i, prof=prof)
+            print(f"case complex medium {i} pass {rep}", flush=True)
+            ref = _oracle(p)
+            err = _rel(_solve(cs3d, p), ref)
+            assert err < _bar(p, ref, 1e-12), (rep, i, err)
