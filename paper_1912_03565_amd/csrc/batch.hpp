@@ -24,12 +24,33 @@ struct BatchArgs {
   int total;
 };
 
+// The work lists and member descriptors are read with vector loads (an opaque offset),
+// then made uniform again with readfirstlane.  As uniform reads the compiler would turn
+// them into scalar loads, and those can return what was at the same address before: the
+// lists of a destroyed batch, or this batch's own before a re-tune rewrote them.
+__device__ __forceinline__ int vload_int(const int* a) {
+  return __builtin_amdgcn_readfirstlane(a[opaque(0)]);
+}
+
+__device__ __forceinline__ ProbDev vload_desc(const ProbDev* a) {
+  static_assert(sizeof(ProbDev) % 4 == 0, "descriptor of whole words");
+  constexpr int N = sizeof(ProbDev) / 4;
+  const int* w = reinterpret_cast<const int*>(a) + opaque(0);
+  union {
+    ProbDev d;
+    int u[N];
+  } v;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v.u[k] = __builtin_amdgcn_readfirstlane(w[k]);
+  return v.d;
+}
+
 // position k of the work list holding `item` (start[k] <= item < start[k+1])
 __device__ __forceinline__ int find_slot(const BatchArgs& b, int item) {
   int lo = 0, hi = b.n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (b.start[mid] <= item) lo = mid;
+    if (vload_int(b.start + mid) <= item) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -81,8 +102,8 @@ __global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
   __shared__ double kt[2 * kZMax];
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
-    const ProbDev& p = b.P[b.perm[k]];
-    const int t = item - b.start[k];
+    const ProbDev p = vload_desc(b.P + vload_int(b.perm + k));
+    const int t = item - vload_int(b.start + k);
     const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRY - 1) / kRY;
     rhs_block<true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win, kt);
   }
@@ -162,8 +183,8 @@ __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
   int curM = -1;
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
-    const ProbDev& p = b.P[b.perm[k]];
-    const int t = item - b.start[k];
+    const ProbDev p = vload_desc(b.P + vload_int(b.perm + k));
+    const int t = item - vload_int(b.start + k);
     if (p.fx != curM) {  // uniform: reload the tables of this transform size
       __syncthreads();
       dispatch_m<MAXM, DENSE>(p.fx, [&](auto mc) {
@@ -193,8 +214,8 @@ __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
   int curM = -1;
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
-    const ProbDev& p = b.P[b.perm[k]];
-    const int g = item - b.start[k];
+    const ProbDev p = vload_desc(b.P + vload_int(b.perm + k));
+    const int g = item - vload_int(b.start + k);
     __syncthreads();  // every line of the previous item is done with the LDS
     if (p.fy != curM) {
       dispatch_m<MAXM, DENSE>(p.fy, [&](auto mc) {

@@ -222,8 +222,12 @@ __device__ __forceinline__ double face_corr(const ProbDev& p, int r, int i, int 
     F = -hz2 * (d4_onesided(c, st, low) - pad) * (1.0 / 240.0);
   }
   if (axis == 2) {
-    if (l == 1 && p.glo) F -= plane9(p.W + 0, p.glo + r * p.g_stride, p.nx, i, j);
-    if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8, p.ghi + r * p.g_stride, p.nx, i, j);
+    // the weights through vector loads (an opaque offset): a uniform read here would
+    // otherwise become a scalar load, which can return what an earlier plan left at the
+    // same address
+    const int o = opaque(0);
+    if (l == 1 && p.glo) F -= plane9(p.W + o, p.glo + r * p.g_stride, p.nx, i, j);
+    if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8 + o, p.ghi + r * p.g_stride, p.nx, i, j);
   }
   return F;
 }

@@ -102,3 +102,20 @@ def test_complex_plans_in_turn_follow_their_own_medium(cs3d):
             ref = _oracle(p)
             err = _rel(_solve(cs3d, p), ref)
             assert err < _bar(p, ref, 1e-12), (rep, i, err)
+
+
+def test_batches_in_turn_follow_their_own_members(cs3d):
+    """Batches of one layout (member sizes and schemes) but different media, each closed
+    before the next opens: the work lists and member descriptors of each sit where its
+    predecessor's were.  Every member matches a single plan of its own."""
+    layout = [("helm6", 63, 31, 17), ("cd4", 127, 63, 9), ("helm4", 63, 63, 12)]
+    for rep in range(2):
+        for i, prof in enumerate(PROFILES):
+            probs = [WL.noise_problem(nx, ny, nz, s, seed=320 + 10 * i + m, prof=prof, boundary=False)
+                     for m, (s, nx, ny, nz) in enumerate(layout)]
+            print(f"case batch medium {i} pass {rep}", flush=True)
+            b = cs3d.Batch([cs3d.batch_member(p) for p in probs], device=DEV)
+            us = [u.cpu().numpy() for u in b.solve([p.f[0].to(DEV) for p in probs])]
+            b.close()
+            for m, p in enumerate(probs):
+                assert _rel(us[m], _solve(cs3d, p)) < 1e-13, (rep, i, m)
