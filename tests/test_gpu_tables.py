@@ -1,12 +1,22 @@
 """The paper's convergence tables reproduced by the HIP path (FP64), through the C ABI.
 
-Section 5.2.2, Tables 4 and 5 (2nd and 4th order, variable k(z) = a - b sin(cz)) and the
-convection-diffusion table of Section 5.2.3: max-error and L2-error of every printed row
-to all printed digits.  Table 6 (6th order): the paper does not define its discrete
-derivatives of f (reading R11), so its rows are matched in magnitude, the HIP path's
-errors equal the oracle's, and the observed order between the two printed sizes is at
-least six (the printed rows give 6.0; this discrete right-hand side gives 7.0 there, its
-N = 125 error carrying a larger h^7 part).
+Section 5.2.2, Tables 4, 5 and 6 (2nd, 4th and 6th order, variable k(z) = a - b sin(cz)) at
+125^3, 250^3 and 500^3, and the convection-diffusion table of Section 5.2.3 at 64^3 ...
+512^3.  Every size runs on the GPU.
+
+* Tables 4 and 5 and the convection-diffusion table: max-err and L2-err to every printed
+  digit (0.75 of the last one), plus the FP64 rounding bound cond * eps * max|u| of the one
+  excited mode's solve, which exceeds a printed unit only at the largest sizes (the printed
+  eighth digit lies below what an FP64 solve resolves there).  The HIP path's errors equal
+  the exact discrete errors of the one-mode reduction (``paper_problems.single_mode``,
+  extended precision) within that bound.
+* Table 6: the paper does not define its discrete derivatives of f (reading R11), so its
+  rows are matched in magnitude, the HIP path's errors equal the oracle's, and the observed
+  order from 250 to 500 lies in [5.8, 6.2] (printed: 6.0; the 125 -> 250 interval is
+  pre-asymptotic for this discrete right-hand side, order 7.0).
+
+Table 6 compares with the oracle's errors, stored for every size (tests/golden/
+oracle_tables.json, written by tests/golden/make_oracle_tables.py from the oracle alone).
 """
 import json
 import math
@@ -17,6 +27,7 @@ import pytest
 import torch
 
 import oracle as O
+import paper_problems as PP
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -38,65 +49,63 @@ def tables(golden_dir):
         return json.load(fh)
 
 
-def _printed_match(ours, printed, digits=8):
-    """|ours - printed| within 0.75 unit of the last printed digit."""
-    e = math.floor(math.log10(abs(printed)))
-    return abs(ours - printed) <= 0.75 * 10.0 ** (e - (digits - 1))
+@pytest.fixture(scope="module")
+def stored(golden_dir):
+    return PP.oracle_tables(golden_dir)
 
 
-def _gpu(cs3d, p):
+def _gpu_errors(cs3d, p):
     plan = cs3d.plan_for_problem(p, device=DEV)
-    gl = None if p.g_lo is None else p.g_lo.to(DEV)
-    gh = None if p.g_hi is None else p.g_hi.to(DEV)
-    u = plan.solve(p.f.to(DEV), gl, gh).cpu().numpy()[0]
+    u = plan.solve(p.f.to(DEV), p.g_lo.to(DEV), p.g_hi.to(DEV)).cpu().numpy()[0]
     st = plan.stats()
     plan.close()
+    del plan
+    torch.cuda.empty_cache()
     assert st["bad_pivots"] == 0
-    return u
+    return O.error_norms(u, p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1]), st
 
 
-@pytest.mark.parametrize("scheme,key", [("helm2", "table4_helm2"), ("helm4", "table5_helm4")])
-@pytest.mark.parametrize("row", [0, 1])
-def test_tables_4_5_all_digits(cs3d, tables, scheme, key, row):
+@pytest.mark.parametrize("scheme,key,row", [(s, k, r) for s, k, rows in (
+    ("helm2", "table4_helm2", 3), ("helm4", "table5_helm4", 3), ("cd4", "cd_table", 4))
+    for r in range(rows)])
+def test_printed_rows_of_tables_4_5_and_cd(cs3d, tables, scheme, key, row):
     ref = tables[key]["rows"][row]
-    p = WL.paper_variable_k(ref["n"], scheme)
-    u = _gpu(cs3d, p)
-    e = O.error_norms(u, p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1])
-    print(f"{key} N={ref['n']}: max {e['max_err']:.8e} (printed {ref['max_err']:.8e}), "
-          f"l2 {e['l2_err_U']:.8e} (printed {ref['l2_err']:.8e})", flush=True)
-    assert _printed_match(e["max_err"], ref["max_err"])
-    assert _printed_match(e["l2_err_U"], ref["l2_err"])
+    n = ref["n"]
+    p = WL.paper_cd(n) if scheme == "cd4" else WL.paper_variable_k(n, scheme)
+    e, st = _gpu_errors(cs3d, p)
+    m = PP.single_mode(scheme, n)
+    b = PP.fp64_bound(m)
+    l2key = "l2_err_u" if scheme == "cd4" else "l2_err_U"  # reading R12
+    print(f"{key} N={n}: max {e['max_err']:.9e} (printed {ref['max_err']:.7e}, exact discrete "
+          f"{m['max_err']:.9e}), l2 {e[l2key]:.9e} (printed {ref['l2_err']:.7e}, exact "
+          f"{m[l2key]:.9e}); mode cond {m['cond']:.3e} -> FP64 bounds {b['max_err']:.2e} (max), "
+          f"{b['l2']:.2e} (L2)", flush=True)
+    assert abs(e["max_err"] - ref["max_err"]) <= PP.printed_bar(ref["max_err"], b["max_err"])
+    assert abs(e[l2key] - ref["l2_err"]) <= PP.printed_bar(ref["l2_err"], b["l2"])
+    assert abs(e["max_err"] - m["max_err"]) <= b["max_err"]
+    assert abs(e[l2key] - m[l2key]) <= b["l2"]
 
 
-@pytest.mark.parametrize("row", [0, 1])
-def test_cd_table_all_digits(cs3d, tables, row):
-    ref = tables["cd_table"]["rows"][row]
-    p = WL.paper_cd(ref["n"])
-    u = _gpu(cs3d, p)
-    e = O.error_norms(u, p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1])
-    print(f"cd N={ref['n']}: max {e['max_err']:.8e} (printed {ref['max_err']:.8e}), "
-          f"l2 {e['l2_err_u']:.8e} (printed {ref['l2_err']:.8e})", flush=True)
-    assert _printed_match(e["max_err"], ref["max_err"])
-    assert _printed_match(e["l2_err_u"], ref["l2_err"])
-
-
-def test_table6_magnitude_order_and_oracle(cs3d, tables):
-    errs = []
+def test_table6_magnitude_order_and_oracle(cs3d, tables, stored):
+    oracle_rows = {r["n"]: r for r in stored["table6_helm6"]["rows"]}
+    errs = {}
     for ref in tables["table6_helm6"]["rows"]:
-        p = WL.paper_variable_k(ref["n"], "helm6")
-        u = _gpu(cs3d, p)
-        ue = p.u_exact[0].numpy()[1:-1, 1:-1, 1:-1]
-        e = O.error_norms(u, ue)
-        res = O.solve(p.scheme, p.f[0].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz, p.gamma,
-                      None if p.g_lo is None else p.g_lo[0].numpy(),
-                      None if p.g_hi is None else p.g_hi[0].numpy())
-        eo = O.error_norms(res.U, ue)
-        print(f"table6 N={ref['n']}: max {e['max_err']:.6e} (oracle {eo['max_err']:.6e}, printed "
-              f"{ref['max_err']:.6e})", flush=True)
+        n = ref["n"]
+        p = WL.paper_variable_k(n, "helm6")
+        e, st = _gpu_errors(cs3d, p)
+        eo = oracle_rows[n]
+        print(f"table6 N={n}: max {e['max_err']:.9e} (oracle {eo['max_err']:.9e}, printed "
+              f"{ref['max_err']:.7e}), l2 {e['l2_err_U']:.9e} (oracle {eo['l2_err_U']:.9e}), "
+              f"min pivot {st['min_abs_pivot']:.3e}", flush=True)
+        # the excited mode's tridiagonal has inf-norm condition number up to 2.9e3 (500^3), so
+        # FP64 rounding moves max-err by up to cond * eps * max|u| = 6e-13: bar 1e-12
         assert abs(e["max_err"] - eo["max_err"]) <= 1e-12
-        assert ref["max_err"] / 3 <= e["max_err"] <= 3 * ref["max_err"]
-        errs.append((ref["n"], e["max_err"]))
-    (n1, e1), (n2, e2) = errs
-    order = math.log(e1 / e2) / math.log((n2 + 1) / (n1 + 1))
-    print(f"table6 observed order {order:.2f}", flush=True)
-    assert order >= 5.5
+        assert abs(e["l2_err_U"] - eo["l2_err_U"]) <= 1e-12
+        lo, hi = (1 / 3, 3) if n == 125 else (0.8, 1.2)
+        assert lo * ref["max_err"] <= e["max_err"] <= hi * ref["max_err"]
+        errs[n] = e["max_err"]
+    order = math.log(errs[250] / errs[500]) / math.log(501 / 251)
+    first = math.log(errs[125] / errs[250]) / math.log(251 / 126)
+    print(f"table6 observed order 125->250 {first:.2f}, 250->500 {order:.2f} (printed 6.00, 6.00)",
+          flush=True)
+    assert 5.8 <= order <= 6.2
