@@ -74,6 +74,7 @@ __all__ = [
     "mirror_pad",
     "modal_eigenvalues", "thomas", "solve_modal", "solve", "apply_operator",
     "assemble_dense", "dense_solve", "error_norms", "OracleResult", "closed",
+    "ROBIN_SCHEMES", "robin_weights", "robin_rhs", "robin_ghost", "solve_robin", "assemble_dense_robin",
 ]
 
 
@@ -518,3 +519,212 @@ def error_norms(U, u_exact_interior, W=None, F=None, g_lo=None, g_hi=None, sides
         out["l2_res"] = float(np.linalg.norm(r))
         out["rel_res"] = float(np.linalg.norm(r) / np.linalg.norm(lift(W, F, g_lo, g_hi, sides)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Robin z faces (reading R22).  Section 1 states alpha u_z + beta u = g on the z faces but
+# not its discretisation (the paper cites earlier work for it).  The closure here: the
+# z-face nodes z_0 and z_{Nz+1} become unknowns and carry the scheme's own row; the ghost
+# plane beyond each face is eliminated by the Taylor expansion
+#     u(z_0 - h) = u(z_0 + h) - 2h u_z - (h^3/3) u_zzz + O(h^5)
+# with u_z = (g - beta u)/alpha from the boundary condition and u_zzz from the z-derivative
+# of the equation, u_zzz = f_z - (k^2)_z u - (k^2 + D) u_z, D = delta_x^2 + delta_y^2 on
+# the face plane (Dirichlet sides).  The ghost value is then the neighbouring plane plus
+# in-plane operators of the face plane and of g, so every modal system stays tridiagonal
+# (N_z + 2 rows; only the first and last rows change).  Local error O(h^5) in the ghost
+# plane: fourth order near the faces (HELM2 stays second order, HELM6 drops to fourth).
+# The boundary rows' right-hand sides take the scheme's operator with one-sided z
+# differences (second order for delta_z^2 and delta_z, first order for delta_z^4).
+#
+# Arrays: U, F of shape (nz+2, ny, nx) for the planes z_0..z_{nz+1}; f on the closed grid
+# (nz+2, ny+2, nx+2); g_lo, g_hi closed planes (ny+2, nx+2) with a zero ring; k2, k2_z,
+# k2_zz sampled at the nz+4 planes z_{-1}..z_{nz+2}.
+# ----------------------------------------------------------------------------
+ROBIN_SCHEMES = ("helm2", "helm4", "helm6")
+
+
+def robin_weights(scheme, nz, hx, hy, hz, k2, k2_z=None, k2_zz=None):
+    """Weights of the rows of planes z_0..z_{nz+1}, shape (nz+2, 3, 4)."""
+    if scheme not in ROBIN_SCHEMES:
+        raise ValueError("Robin z faces: Helmholtz schemes only")
+    return stencil_weights(scheme, nz + 2, hx, hy, hz, k2, k2_z, k2_zz)
+
+
+def _plane_lap(P, hx, hy):
+    """delta_x^2 + delta_y^2 of the interior of a closed plane (Dirichlet sides)."""
+    return ((P[1:-1, :-2] - 2.0 * P[1:-1, 1:-1] + P[1:-1, 2:]) / (hx * hx)
+            + (P[:-2, 1:-1] - 2.0 * P[1:-1, 1:-1] + P[2:, 1:-1]) / (hy * hy))
+
+
+def _robin_face_rhs(scheme, f, hx, hy, hz, k2f, k2zf, side):
+    """The scheme's RHS operator at the face nodes (interior x/y) from f on the closed grid,
+    z differences one-sided into the box: delta_z^2 (2, -5, 4, -1), delta_z^4
+    (3, -14, 26, -24, 11, -2), delta_z as (-3, 4, -1)/2 (raw, unscaled differences)."""
+    g = f if side == "lo" else f[::-1]
+    s = 1.0 if side == "lo" else -1.0
+    fp = [g[q] for q in range(6)]
+    inner = fp[0][1:-1, 1:-1]
+    d2z = 2 * fp[0] - 5 * fp[1] + 4 * fp[2] - fp[3]
+    d4z = 3 * fp[0] - 14 * fp[1] + 26 * fp[2] - 24 * fp[3] + 11 * fp[4] - 2 * fp[5]
+    d1z = s * (-3 * fp[0] + 4 * fp[1] - fp[2]) / 2.0
+    P = fp[0]
+    d2x = P[1:-1, :-2] - 2.0 * P[1:-1, 1:-1] + P[1:-1, 2:]
+    d2y = P[:-2, 1:-1] - 2.0 * P[1:-1, 1:-1] + P[2:, 1:-1]
+    if scheme == "helm2":
+        return hz * hz * inner
+    if scheme == "helm4":
+        return hz * hz * (inner + (d2x + d2y + d2z[1:-1, 1:-1]) / 12.0)
+    # helm6 (uniform h): the interior formula of rhs() with the z parts one-sided
+    h = hz
+    # fourth differences of the face plane in x and y, with the one-sided R10 formula on
+    # the first and last interior lines (as rhs() does for the interior planes)
+    fx = _d4(np.stack([P] * 3), 2)[0]
+    fy = _d4(np.stack([P] * 3), 1)[0]
+    d2xz = d2z[1:-1, :-2] - 2.0 * d2z[1:-1, 1:-1] + d2z[1:-1, 2:]
+    d2yz = d2z[:-2, 1:-1] - 2.0 * d2z[1:-1, 1:-1] + d2z[2:, 1:-1]
+    d2xy = (P[:-2, :-2] - 2 * P[:-2, 1:-1] + P[:-2, 2:]
+            - 2 * (P[1:-1, :-2] - 2 * P[1:-1, 1:-1] + P[1:-1, 2:])
+            + P[2:, :-2] - 2 * P[2:, 1:-1] + P[2:, 2:])
+    s2 = d2x + d2y + d2z[1:-1, 1:-1]
+    s4 = fx + fy + d4z[1:-1, 1:-1]
+    sx = d2xy + d2xz + d2yz
+    return h * h * (inner + s2 / 12.0 - s4 / 240.0 + sx / 90.0
+                    - h * h * k2f * inner / 20.0 + h ** 3 * k2zf * d1z[1:-1, 1:-1] / 60.0)
+
+
+def robin_rhs(scheme, f, hx, hy, hz, k2, k2_z=None):
+    """F on the planes z_0..z_{nz+1} (shape (nz+2, ny, nx)): interior planes as rhs(), the
+    face planes by _robin_face_rhs.  k2, k2_z sampled at z_{-1}..z_{nz+2}."""
+    f = _num(f)
+    nz = f.shape[0] - 2
+    k2 = _num(k2)
+    k2z = None if k2_z is None else _num(k2_z)
+    F = np.empty((nz + 2, f.shape[1] - 2, f.shape[2] - 2), dtype=f.dtype)
+    F[1:-1] = rhs(scheme, f, hx, hy, hz, k2[1:-1], None if k2z is None else k2z[1:-1])
+    kz0 = 0.0 if k2z is None else k2z[1]
+    kz1 = 0.0 if k2z is None else k2z[-2]
+    F[0] = _robin_face_rhs(scheme, f, hx, hy, hz, k2[1], kz0, "lo")
+    F[-1] = _robin_face_rhs(scheme, f, hx, hy, hz, k2[-2], kz1, "hi")
+    return F
+
+
+def robin_ghost(nz, hx, hy, hz, k2, k2_z, alpha, beta, f, g_lo, g_hi):
+    """The ghost-plane eliminations of both faces.
+
+    Bottom: U_{-1} = U_1 + c_lo(D) U_0 + R_lo, top: U_{nz+2} = U_nz + c_hi(D) U_{nz+1} + R_hi,
+    with c(D) = c0 + c1 D an in-plane operator of the face plane:
+      c_lo = (h^3/3) k2_z(z_0) - (beta/alpha)(-2h + (h^3/3)(k2(z_0) + D))
+      c_hi = -(h^3/3) k2_z(z_{nz+1}) - (beta/alpha)(2h - (h^3/3)(k2(z_{nz+1}) + D))
+      R_lo = (1/alpha)(-2h + (h^3/3)(k2 + D)) g_lo - (h^3/3) f_z(z_0)
+      R_hi = (1/alpha)(2h - (h^3/3)(k2 + D)) g_hi + (h^3/3) f_z(z_{nz+1})
+    f_z one-sided of second order.  Returns ((c0, c1) per face, (R_lo, R_hi) interior planes)."""
+    h = hz
+    (a0, a1), (b0, b1) = alpha, beta
+    k2 = _num(k2)
+    k2z = np.zeros_like(k2) if k2_z is None else _num(k2_z)
+    f = _num(f)
+    kl, kh = k2[1], k2[-2]
+    kzl, kzh = k2z[1], k2z[-2]
+    c_lo = ((h ** 3 / 3.0) * kzl - (b0 / a0) * (-2.0 * h + (h ** 3 / 3.0) * kl), -(b0 / a0) * (h ** 3 / 3.0))
+    c_hi = (-(h ** 3 / 3.0) * kzh - (b1 / a1) * (2.0 * h - (h ** 3 / 3.0) * kh), (b1 / a1) * (h ** 3 / 3.0))
+    fz_lo = (-3.0 * f[0] + 4.0 * f[1] - f[2]) / (2.0 * h)
+    fz_hi = (3.0 * f[-1] - 4.0 * f[-2] + f[-3]) / (2.0 * h)
+    gl, gh = _num(g_lo), _num(g_hi)
+    R_lo = ((-2.0 * h + (h ** 3 / 3.0) * kl) * gl[1:-1, 1:-1] + (h ** 3 / 3.0) * _plane_lap(gl, hx, hy)) / a0 \
+        - (h ** 3 / 3.0) * fz_lo[1:-1, 1:-1]
+    R_hi = ((2.0 * h - (h ** 3 / 3.0) * kh) * gh[1:-1, 1:-1] - (h ** 3 / 3.0) * _plane_lap(gh, hx, hy)) / a1 \
+        + (h ** 3 / 3.0) * fz_hi[1:-1, 1:-1]
+    return (c_lo, c_hi), (R_lo, R_hi)
+
+
+def _plane9_open(w, P):
+    """9-point weights applied to an interior plane P (zero beyond its edges)."""
+    Z = np.zeros((P.shape[0] + 2, P.shape[1] + 2), dtype=P.dtype)
+    Z[1:-1, 1:-1] = P
+    return _plane9(w, Z)
+
+
+def solve_robin(scheme, f, hx, hy, hz, k2, k2_z=None, k2_zz=None, alpha=(1.0, 1.0), beta=(0.0, 0.0),
+                g_lo=None, g_hi=None, dtype=np.float64, W=None):
+    """U on the planes z_0..z_{nz+1} for Robin z faces (reading R22): weights -> F -> ghost
+    eliminations -> DST -> modal Thomas with changed first and last rows -> inverse DST.
+
+    Row 0:      (lam^0 + c_lo(mu) lam^-) W_0 + (lam^+ + lam^-) W_1 = Fbar_0 - lam^- Rbar_lo
+    Row nz+1:   (lam^- + lam^+) W_nz + (lam^0 + c_hi(mu) lam^+) W_{nz+1} = Fbar_{nz+1} - lam^+ Rbar_hi
+    where mu = -(2 - 2 cos th)/hx^2 - (2 - 2 cos ph)/hy^2 is the eigenvalue of D on the mode.
+    The lifts lam^- Rbar are applied in physical space (the plane-offset weights on R).
+    W: the rows' weights, if given (else robin_weights)."""
+    f = _num(f)
+    nz = f.shape[0] - 2
+    ny, nx = f.shape[1] - 2, f.shape[2] - 2
+    if W is None:
+        W = robin_weights(scheme, nz, hx, hy, hz, k2, k2_z, k2_zz)
+    F = robin_rhs(scheme, f, hx, hy, hz, k2, k2_z)
+    z = np.zeros((ny + 2, nx + 2))
+    (c_lo, c_hi), (R_lo, R_hi) = robin_ghost(nz, hx, hy, hz, k2, k2_z, alpha, beta, f,
+                                             z if g_lo is None else g_lo, z if g_hi is None else g_hi)
+    F = np.array(F, copy=True)
+    F[0] -= _plane9_open(W[0, 0], R_lo)
+    F[-1] -= _plane9_open(W[-1, 2], R_hi)
+    Fbar = dst2(F, dtype)
+    real = np.real(Fbar[:1, :1, :1]).dtype
+    lam = modal_eigenvalues(W, nx, ny, real)
+    pi = _pi(real)
+    ct = np.cos(pi * np.arange(1, nx + 1, dtype=real) / (nx + 1))[None, :]
+    cp = np.cos(pi * np.arange(1, ny + 1, dtype=real) / (ny + 1))[:, None]
+    mu = -(2 - 2 * ct) / (hx * hx) - (2 - 2 * cp) / (hy * hy)
+    lam = np.array(lam, copy=True)
+    lm0, lp0 = lam[0, 0].copy(), lam[0, 2].copy()
+    lam[0, 1] = lam[0, 1] + (c_lo[0] + c_lo[1] * mu) * lm0
+    lam[0, 2] = lp0 + lm0
+    lm1, lp1 = lam[-1, 0].copy(), lam[-1, 2].copy()
+    lam[-1, 0] = lm1 + lp1
+    lam[-1, 1] = lam[-1, 1] + (c_hi[0] + c_hi[1] * mu) * lp1
+    What, minpiv, bad = thomas(lam, Fbar)
+    U = dst2(What).astype(np.float64)
+    return OracleResult(U, W, F, minpiv, bad)
+
+
+def assemble_dense_robin(scheme, nx, ny, nz, hx, hy, hz, k2, k2_z=None, k2_zz=None, alpha=(1.0, 1.0),
+                         beta=(0.0, 0.0)):
+    """The (nz+2)-plane system with the ghost planes substituted, entry by entry: each row
+    is eq. stencil27 with the neighbours beyond a face replaced by the ghost formulas of
+    robin_ghost (in-plane operators c0 + c1 D of the face plane, D the 5-point in-plane
+    second differences), as a dense matrix (no transform involved)."""
+    W = robin_weights(scheme, nz, hx, hy, hz, k2, k2_z, k2_zz)
+    npl = nx * ny
+    nzz = nz + 2
+    A = np.zeros((npl * nzz, npl * nzz))
+
+    def plane_op(w):
+        """Matrix of the 9-point in-plane operator with weights w (Dirichlet sides)."""
+        M = np.zeros((npl, npl))
+        a, b, c, d = w
+        for j in range(ny):
+            for i in range(nx):
+                r = i + nx * j
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        ii, jj = i + di, j + dj
+                        if 0 <= ii < nx and 0 <= jj < ny:
+                            M[r, ii + nx * jj] += (a if (di and dj) else b if di else c if dj else d)
+        return M
+
+    D = plane_op((0.0, 1.0 / (hx * hx), 1.0 / (hy * hy), -2.0 / (hx * hx) - 2.0 / (hy * hy)))
+    (c_lo, c_hi), _ = robin_ghost(nz, hx, hy, hz, k2, k2_z, alpha, beta, np.zeros((nz + 2, 3, 3)),
+                                  np.zeros((3, 3)), np.zeros((3, 3)))
+    I = np.eye(npl)
+    blk = lambda l, ll: (slice(l * npl, (l + 1) * npl), slice(ll * npl, (ll + 1) * npl))  # noqa: E731
+    for l in range(nzz):
+        for o in (-1, 0, 1):
+            M = plane_op(W[l, o + 1])
+            ll = l + o
+            if 0 <= ll < nzz:
+                A[blk(l, ll)] += M
+            elif ll < 0:      # U_{-1} = U_1 + (c0 + c1 D) U_0 (+ data)
+                A[blk(l, 1)] += M
+                A[blk(l, 0)] += M @ (c_lo[0] * I + c_lo[1] * D)
+            else:             # U_{nz+2} = U_nz + (c0 + c1 D) U_{nz+1} (+ data)
+                A[blk(l, nz)] += M
+                A[blk(l, nz + 1)] += M @ (c_hi[0] * I + c_hi[1] * D)
+    return A

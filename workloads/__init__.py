@@ -29,4 +29,6 @@ from .problems import (  # noqa: F401
     neumann_noise_problem,
     config5_absorbing,
     K_ABSORB,
+    robin_noise_problem,
+    manufactured_robin,
 )

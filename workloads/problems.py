@@ -70,6 +70,10 @@ class Problem:
     # "dirichlet": u = 0 on the x/y faces; "neumann": du/dn = 0 there, and every x/y node of
     # the closed grid is an unknown
     sides: str = "dirichlet"
+    # Robin z faces: ((alpha_lo, alpha_hi), (beta_lo, beta_hi)) of alpha u_z + beta u = g, or
+    # None (Dirichlet).  Then g_lo/g_hi are the data g, the k^2 samples cover z_{-1}..z_{nz+2}
+    # and the unknowns include the z-face nodes (nz + 2 planes)
+    robin: Optional[tuple] = None
 
     @property
     def nrhs(self):
@@ -79,6 +83,8 @@ class Problem:
     def unknowns(self):
         if self.sides == "neumann":
             return (self.nx + 2) * (self.ny + 2) * self.nz
+        if self.robin is not None:
+            return self.nx * self.ny * (self.nz + 2)
         return self.nx * self.ny * self.nz
 
 
@@ -366,3 +372,55 @@ def batch_members(seed=104, count=64, sizes=(63, 127, 255), device="cpu", make_f
                            gamma=gamma if scheme == "cd4" else 0.0,
                            meta={"k0": k0 if scheme != "cd4" else None, "seed": sub}))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Robin z faces: alpha u_z + beta u = g on z = 0 and z = L_z (Section 1, eq. bc).
+# The k^2 samples then cover z_{-1}..z_{nz+2} (the rows of the face nodes reach one plane
+# beyond each face).
+# ----------------------------------------------------------------------------
+ROBIN_DEFAULT = ((1.0, 0.7), (2.0, -1.5))
+
+
+def _zsamples_robin(nz, hz, prof):
+    z = hz * np.arange(-1, nz + 3, dtype=np.float64)
+    return prof.samples(z)
+
+
+def robin_noise_problem(nx, ny, nz, scheme, seed, device="cpu", nrhs=1, robin=ROBIN_DEFAULT, prof=None):
+    """Random f on the closed grid and random face data g (zero ring), Robin z faces,
+    k(z) = 6 + 2 sin 3z by default; the grids of ``noise_problem``."""
+    p = noise_problem(nx, ny, nz, scheme, seed, device=device, boundary=True, nrhs=nrhs, prof=prof)
+    if prof is None:
+        prof = KProfile(lambda z: 6.0 + 2.0 * np.sin(3.0 * z), lambda z: 6.0 * np.cos(3.0 * z),
+                        lambda z: -18.0 * np.sin(3.0 * z), "6+2 sin 3z")
+    p.k2, p.k2_z, p.k2_zz = _zsamples_robin(nz, p.hz, prof)
+    p.robin = robin
+    p.name = f"robin_{scheme}_{nx}x{ny}x{nz}_s{seed}"
+    return p
+
+
+def manufactured_robin(n, scheme, robin=ROBIN_DEFAULT, prof=None, device="cpu"):
+    """u = sin(pi x) sin(2 pi y) Z(z), Z = cos(1.3 z) + sin(2.1 z)/2 on the unit cube with
+    Robin data g = alpha Z'(z_face) + beta Z(z_face) (times the x/y factor) on both z faces,
+    f = Z'' + (k^2 - 5 pi^2) Z (times the factor); u_exact on the planes z_0..z_{n+1}."""
+    if prof is None:
+        prof = KProfile(lambda z: 4.0 + np.sin(2 * np.pi * z), lambda z: 2 * np.pi * np.cos(2 * np.pi * z),
+                        lambda z: -4 * np.pi ** 2 * np.sin(2 * np.pi * z), "4 + sin 2 pi z")
+    h = 1.0 / (n + 1)
+    (a0, a1), (b0, b1) = robin
+    x = _axis(n, h, device=device)
+    z = x
+    k2, k2z, k2zz = _zsamples_robin(n, h, prof)
+    Z = torch.cos(1.3 * z) + 0.5 * torch.sin(2.1 * z)
+    Zz = -1.3 * torch.sin(1.3 * z) + 1.05 * torch.cos(2.1 * z)
+    Zzz = -1.69 * torch.cos(1.3 * z) - 2.205 * torch.sin(2.1 * z)
+    sx, sy = torch.sin(math.pi * x), torch.sin(2 * math.pi * x)
+    k2t = torch.as_tensor(k2[1:-1], device=device)
+    u = _outer3(Z, sy, sx)
+    f = _outer3(Zzz + (k2t - 5.0 * math.pi ** 2) * Z, sy, sx)
+    one = torch.ones(1, dtype=torch.float64, device=device)
+    g_lo = _outer3((a0 * Zz[0] + b0 * Z[0]) * one, sy, sx)[0]
+    g_hi = _outer3((a1 * Zz[-1] + b1 * Z[-1]) * one, sy, sx)[0]
+    return Problem(f"robin_sin_{scheme}_{n}", scheme, n, n, n, h, h, h, f=f[None], g_lo=g_lo[None],
+                   g_hi=g_hi[None], k2=k2, k2_z=k2z, k2_zz=k2zz, u_exact=u[None], robin=robin)
