@@ -5,13 +5,15 @@ followed by its imaginary part.  The cases span both transform paths (FFT length
 1024 with one- and two-wave lines, dense sine sums), every Helmholtz scheme, non-cubic
 grids, complex z-face data, a single plane and several right-hand sides.  The oracle
 solves the same complex discrete system with extended-precision transforms and Thomas
-sweeps; the bar is that of the real FP64 path.
+sweeps; the bar is that of the real FP64 path, element by element and in the 2-norm
+(``parity.py``).
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
+import parity as PT
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -26,10 +28,6 @@ def cs3d():
         pytest.skip("no HIP device")
     import paper_1912_03565_amd as m
     return m
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def planar(t):
@@ -75,23 +73,23 @@ CASES = [
 def test_complex_k_matches_oracle(cs3d, scheme, nx, ny, nz):
     p = WL.complex_noise_problem(nx, ny, nz, scheme, seed=3000 + nx + 7 * ny + 13 * nz)
     print(f"case complex {scheme} {nx}x{ny}x{nz}", flush=True)
-    u, st = _gpu(cs3d, p)
     ref = _oracle(p)
-    u64 = _oracle(p, dtype=np.float64).U
-    bar = max(TOL_FP64, 4.0 * _rel(u64, ref.U))
-    err = _rel(u[0], ref.U)
-    print(f"  rel err {err:.3e} (bar {bar:.1e}), |Im U|/|U| {np.linalg.norm(ref.U.imag) / np.linalg.norm(ref.U):.2f}, "
+    bar = PT.oracle_bar(PT.problem_kw(p), ref.U)
+    u, st = _gpu(cs3d, p)
+    PT.check(f"complex {scheme} {nx}x{ny}x{nz}", u[0], ref.U, bar)
+    print(f"  |Im U|/|U| {np.linalg.norm(ref.U.imag) / np.linalg.norm(ref.U):.2f}, "
           f"min pivot {st['min_abs_pivot']:.3e} (oracle {ref.minpiv:.3e})", flush=True)
-    assert err < bar
     assert st["bad_pivots"] == 0
     assert abs(st["min_abs_pivot"] - ref.minpiv) <= 1e-9 * max(1.0, ref.minpiv)
 
 
 def test_complex_several_rhs_and_assembled(cs3d):
     p = WL.complex_noise_problem(127, 63, 12, "helm6", seed=77, nrhs=3)
+    refs = [_oracle(p, r).U for r in range(3)]
+    bars = [PT.oracle_bar(PT.problem_kw(p, r), refs[r]) for r in range(3)]
     u, _ = _gpu(cs3d, p, nrhs=3)
     for r in range(3):
-        assert _rel(u[r], _oracle(p, r).U) < TOL_FP64
+        PT.check(f"complex rhs {r}", u[r], refs[r], bars[r])
     # the assembled path: the oracle's lifted F of right-hand side 1
     W = O.stencil_weights(p.scheme, p.nz, p.hx, p.hy, p.hz, p.k2, p.k2_z, p.k2_zz)
     F = O.lift(W, O.rhs(p.scheme, p.f[1].numpy(), p.hx, p.hy, p.hz, p.k2, p.k2_z),
@@ -99,7 +97,7 @@ def test_complex_several_rhs_and_assembled(cs3d):
     plan = cs3d.plan_for_problem(p, device=DEV, max_rhs=1)
     ua = unplanar(plan.solve_assembled(planar(torch.from_numpy(F)[None])))
     plan.close()
-    assert _rel(ua[0], u[1]) < 1e-13
+    PT.check("assembled vs closed-grid path", ua[0], u[1], PT.Bar.fixed(1e-13))
 
 
 def test_complex_conjugate_medium(cs3d):
@@ -111,7 +109,7 @@ def test_complex_conjugate_medium(cs3d):
     pc.f = p.f
     pc.k2, pc.k2_z, pc.k2_zz = np.conj(p.k2), np.conj(p.k2_z), np.conj(p.k2_zz)
     u2, _ = _gpu(cs3d, pc)
-    assert _rel(u2[0], np.conj(u1[0])) < 1e-13
+    PT.check("conjugate medium", u2[0], np.conj(u1[0]), PT.Bar.fixed(1e-13))
     assert np.linalg.norm(u1[0].imag) > 1e-3 * np.linalg.norm(u1[0])
 
 
@@ -127,4 +125,4 @@ def test_complex_plan_with_real_k_equals_real_solves(cs3d):
     pc.k2 = p.k2.astype(np.complex128)
     pc.f = torch.complex(p.f, fi)
     uc, _ = _gpu(cs3d, pc)
-    assert _rel(uc[0], ure + 1j * uim) < 1e-13
+    PT.check("complex plan, real k", uc[0], ure + 1j * uim, PT.Bar.fixed(1e-13))

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import oracle as O
+import parity as PT
 import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -42,10 +43,6 @@ def cs3d():
     return m
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 def _oracle(p, sides="dirichlet", dtype=np.longdouble):
     gl = None if p.g_lo is None else p.g_lo[0].numpy()
     gh = None if p.g_hi is None else p.g_hi[0].numpy()
@@ -54,9 +51,9 @@ def _oracle(p, sides="dirichlet", dtype=np.longdouble):
 
 
 def _bar(p, ref, tol, sides="dirichlet"):
-    """tol, or four times the plain FP64 oracle's own error where the medium makes that
-    larger (the parity suite's bar)."""
-    return max(tol, 4.0 * _rel(_oracle(p, sides, np.float64), ref))
+    """tol, or four times the FP64 noise floor where the medium makes that larger (the
+    parity suite's bar, parity.oracle_bar), per norm."""
+    return PT.oracle_bar(PT.problem_kw(p), ref, tol)
 
 
 def _dev(t, cplx):
@@ -89,8 +86,8 @@ def test_real_plans_in_turn_follow_their_own_medium(cs3d, path):
                 sides = "dirichlet"
             print(f"case {path} medium {i} pass {rep}", flush=True)
             ref = _oracle(p, sides)
-            err = _rel(_solve(cs3d, p, **kw), ref)
-            assert err < _bar(p, ref, 1e-10 if path == "mixed" else 1e-12, sides), (path, rep, i, err)
+            bar = _bar(p, ref, 1e-10 if path == "mixed" else 1e-12, sides)
+            PT.check(f"{path} medium {i} pass {rep}", _solve(cs3d, p, **kw), ref, bar)
 
 
 def test_complex_plans_in_turn_follow_their_own_medium(cs3d):
@@ -100,8 +97,7 @@ def test_complex_plans_in_turn_follow_their_own_medium(cs3d):
             p = WL.complex_noise_problem(nx, ny, nz, "helm6", seed=310 + i, prof=prof)
             print(f"case complex medium {i} pass {rep}", flush=True)
             ref = _oracle(p)
-            err = _rel(_solve(cs3d, p), ref)
-            assert err < _bar(p, ref, 1e-12), (rep, i, err)
+            PT.check(f"complex medium {i} pass {rep}", _solve(cs3d, p), ref, _bar(p, ref, 1e-12))
 
 
 def test_batches_in_turn_follow_their_own_members(cs3d):
@@ -118,4 +114,4 @@ def test_batches_in_turn_follow_their_own_members(cs3d):
             us = [u.cpu().numpy() for u in b.solve([p.f[0].to(DEV) for p in probs])]
             b.close()
             for m, p in enumerate(probs):
-                assert _rel(us[m], _solve(cs3d, p)) < 1e-13, (rep, i, m)
+                PT.check(f"batch member {m} vs own plan", us[m], _solve(cs3d, p), PT.Bar.fixed(1e-13))
