@@ -79,9 +79,12 @@ typedef enum {
 
 typedef enum {
   CS3D_FP64 = 0,        /* every stage in FP64 */
-  CS3D_MIXED_FP32 = 1   /* FP32 line transforms and FP32 intermediates, FP64 tridiagonal
-                           solves, FP64 27-point residual (computed in FP64, handed to the
-                           FP32 correction solve in FP32) and FP64 update of u */
+  CS3D_MIXED_FP32 = 1   /* FP32 line transforms and FP32 intermediates in HBM, tridiagonal
+                           LU arithmetic in FP64 (eigenvalues, pivots, c' and d' formed in
+                           FP64; c' stored in FP64, d' rounded to FP32 between the forward
+                           and the backward sweep, like the other FP32 intermediates), FP64
+                           27-point residual (computed in FP64, handed to the FP32 correction
+                           solve in FP32) and FP64 update of u */
 } cs3d_precision;
 
 /* Conditions on the x and y faces. */
@@ -95,6 +98,23 @@ enum {
                                derivatives of f to vanish there.  FP64, real k, plans only;
                                nx + 2 and ny + 2 at most 1023 (FFT path where nx + 1 is a
                                power of two in 64..512, direct cosine sums otherwise) */
+};
+
+/* Conditions on the z faces. */
+enum {
+  CS3D_ZFACES_DIRICHLET = 0, /* u = g (the data of cs3d_solve lifted into rows 1 and nz) */
+  CS3D_ZFACES_ROBIN = 1      /* alpha u_z + beta u = g (Section 1, eq. bc, real alpha, beta):
+                                the z-face nodes z_0 and z_{nz+1} are unknowns too, so
+                                interior arrays hold nz + 2 planes (z_0 .. z_{nz+1}); each
+                                face node carries the scheme's row, the ghost plane beyond it
+                                eliminated by u(z_0 - h) = u(z_0 + h) - 2h u_z - (h^3/3) u_zzz
+                                with u_z from the condition and u_zzz from the equation
+                                (fourth order near the faces: HELM2 keeps 2, HELM4 4, HELM6
+                                drops to 4).  The modal systems keep N_z + 2 rows and only
+                                their first and last rows change.  k2, k2_z (required) and
+                                k2_zz then hold nz + 4 samples at z_{-1} .. z_{nz+2}.  HELM2 /
+                                HELM4 / HELM6, FP64, real k, Dirichlet sides, plans only
+                                (else E_UNSUPPORTED); cs3d_residual is unsupported */
 };
 
 typedef struct {
@@ -124,6 +144,11 @@ typedef struct {
                               CS3D_SIDES_NEUMANN; Neumann with mixed precision, complex k or
                               a batch gives E_UNSUPPORTED, with nx + 2 or ny + 2 > 1023
                               E_INVAL */
+  int zfaces;              /* CS3D_ZFACES_DIRICHLET (0, the default of a zeroed desc) or
+                              CS3D_ZFACES_ROBIN */
+  double robin_alpha[2];   /* Robin z faces: alpha of the faces z = L_z^l and z = L_z^r
+                              (finite, non-zero) */
+  double robin_beta[2];    /* Robin z faces: beta of the two faces (finite) */
 } cs3d_desc;
 
 typedef struct {
@@ -164,6 +189,9 @@ cs3d_status cs3d_set_workspace(cs3d_plan plan, void* dev_workspace, size_t bytes
  * documented in the design notes), the z-face data are lifted into the first and last
  * rows through the plane-offset weights, and the solution is written to the interior
  * array dev_u.  dev_g_lo / dev_g_hi may be NULL (zero data).
+ * Robin z faces (desc.zfaces = CS3D_ZFACES_ROBIN): dev_g_lo / dev_g_hi hold the data g of
+ * alpha u_z + beta u = g (closed planes, zero ring), and dev_u receives nz + 2 planes, the
+ * face nodes z_0 and z_{nz+1} included; f keeps its closed-grid shape.
  * Errors: E_INVAL (NULL plan, f or u; nrhs out of range; scheme CS3D_WEIGHTS, which has
  * no RHS operator - use cs3d_solve_assembled), E_WORKSPACE, E_DEVICE. */
 cs3d_status cs3d_solve(cs3d_plan plan, int nrhs, const double* dev_f, const double* dev_g_lo,
@@ -212,6 +240,8 @@ typedef struct {
                     for FP64, 2 for mixed precision).
                     Their tridiagonal systems share the modal eigenvalues, the pivots and
                     each read of c'; transform sizes whose lanes hold 16 modes use 1. */
+  int xwpl;      /* x passes of a plan where N_x+1 is 512 or 1024: waves per line, 1 or 2
+                    (1024 threads per workgroup, half a line per lane); other sizes use 1 */
 } cs3d_tuning;
 
 /* Current launch-shape choices of a plan.  Errors: E_INVAL (NULL argument). */

@@ -26,8 +26,10 @@ struct BatchArgs {
 
 // The work lists and member descriptors are read with vector loads (an opaque offset),
 // then made uniform again with readfirstlane.  As uniform reads the compiler would turn
-// them into scalar loads, and those can return what was at the same address before: the
-// lists of a destroyed batch, or this batch's own before a re-tune rewrote them.
+// them into scalar loads; with plan tables read that way, plans created after others
+// had been destroyed gave wrong results (the cause was not isolated: a stale scalar-cache
+// line is one reading, a read of uninitialised workspace another), and these lists are
+// rewritten in place by a re-tune, so they stay on the vector path.
 __device__ __forceinline__ int vload_int(const int* a) {
   return __builtin_amdgcn_readfirstlane(a[opaque(0)]);
 }

@@ -55,6 +55,7 @@ struct Tuning {
   int order = 1;         // batches: members by decreasing cost per item
   int graph = 1;         // batches: captured graph replay
   int yrhs = 1;          // right-hand sides per y-pass workgroup (1, 2 or 4)
+  int xwpl = 1;          // waves per x-line where the FFT allows two (M >= 512)
 };
 
 struct cs3d_plan_s {
@@ -77,6 +78,10 @@ struct cs3d_plan_s {
   hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // Robin z faces: d.nz counts the system's planes (nz + 2), nz_phys the interior ones
+  bool robin = false;
+  int nz_phys = 0;
+  double rb[4] = {0.0, 0.0, 0.0, 0.0};
   // per-pass timing ring: kRing solves x (kMaxMarks + 1) events; interval k of a solve
   // belongs to stage ring_sid[...]
   std::vector<hipEvent_t> ring;
@@ -313,6 +318,15 @@ static cs3d_status validate(const cs3d_desc* d) {
     if (d->nx + 2 > kMaxN || d->ny + 2 > kMaxN) return CS3D_E_INVAL;
     if (d->precision != CS3D_FP64 || d->k2_im) return CS3D_E_UNSUPPORTED;
   }
+  if (d->zfaces != CS3D_ZFACES_DIRICHLET && d->zfaces != CS3D_ZFACES_ROBIN) return CS3D_E_INVAL;
+  if (d->zfaces == CS3D_ZFACES_ROBIN) {
+    if (d->scheme != CS3D_HELM2 && d->scheme != CS3D_HELM4 && d->scheme != CS3D_HELM6) return CS3D_E_UNSUPPORTED;
+    if (d->precision != CS3D_FP64 || d->k2_im || d->sides != CS3D_SIDES_DIRICHLET) return CS3D_E_UNSUPPORTED;
+    if (!d->k2_z || d->nz < 4) return CS3D_E_INVAL;
+    for (int q = 0; q < 2; ++q)
+      if (!std::isfinite(d->robin_alpha[q]) || d->robin_alpha[q] == 0.0 || !std::isfinite(d->robin_beta[q]))
+        return CS3D_E_INVAL;
+  }
   if (d->k2_im) {  // complex k: Helmholtz schemes, FP64
     if (d->scheme == CS3D_HELM6 && (!d->k2_z_im || !d->k2_zz_im)) return CS3D_E_INVAL;
     if (d->scheme != CS3D_HELM2 && d->scheme != CS3D_HELM4 && d->scheme != CS3D_HELM6) return CS3D_E_UNSUPPORTED;
@@ -364,6 +378,15 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
     p->d.nx = desc->nx + 2;  // the side nodes are unknowns
     p->d.ny = desc->ny + 2;
   }
+  p->robin = desc->zfaces == CS3D_ZFACES_ROBIN;
+  p->nz_phys = desc->nz;
+  // the system's z planes: with Robin faces the face nodes z_0, z_{nz+1} are unknowns, and
+  // the rows and samples of the desc cover them (the samples z_{-1} .. z_{nz+2})
+  cs3d_desc wd = *desc;
+  if (p->robin) {
+    p->d.nz = desc->nz + 2;
+    wd.nz = desc->nz + 2;
+  }
   p->ldy = ((p->d.ny + 1 + 15) / 16) * 16;
   p->tune.ywpl = (p->fy == 1024) ? 2 : 1;
   // long z-columns: fewer halo planes per workgroup; FP32 transforms leave registers for
@@ -372,14 +395,26 @@ extern "C" cs3d_status cs3d_plan_create(const cs3d_desc* desc, void* hip_stream,
   p->tune.zchunk = desc->nz >= 512 ? (mixed ? 128 : 64) : kZChunk;
   p->tune.yrhs = mixed ? 2 : 1;
   std::vector<double> hWi;
-  st = p->cplx ? build_weights_c(*desc, p->hW, hWi) : build_weights(*desc, p->hW);
+  st = p->cplx ? build_weights_c(wd, p->hW, hWi) : build_weights(wd, p->hW);
   if (st != CS3D_OK) {
     plan_free(p);
     return st;
   }
   hipStream_t s = (hipStream_t)hip_stream;
-  const int nzp = desc->nz + 2;
+  const int nzp = p->d.nz + 2;
   std::vector<double> k2(nzp, 0.0), k2z(nzp, 0.0);
+  if (p->robin) {
+    // ghost-plane elimination of the two faces, as c0 + c1 D (D: in-plane 5-point Laplacian)
+    const double h = desc->hz, h3 = h * h * h / 3.0;
+    const double kl = desc->k2[1], kzl = desc->k2_z[1];              // z_0
+    const double kh = desc->k2[nzp - 2], kzh = desc->k2_z[nzp - 2];  // z_{nz+1}
+    const double ql = desc->robin_beta[0] / desc->robin_alpha[0];
+    const double qh = desc->robin_beta[1] / desc->robin_alpha[1];
+    p->rb[0] = h3 * kzl - ql * (-2.0 * h + h3 * kl);
+    p->rb[1] = -ql * h3;
+    p->rb[2] = -h3 * kzh - qh * (2.0 * h - h3 * kh);
+    p->rb[3] = qh * h3;
+  }
   if (desc->k2)
     for (int i = 0; i < nzp; ++i) k2[i] = desc->k2[i];
   if (desc->k2_z)
@@ -505,6 +540,14 @@ static size_t lds_bytes_x_t(const cs3d_plan p) {
   return (a > b ? a : b) + tw_bytes<T, MX>();
 }
 
+// the x passes with two waves per line
+template <typename T, int MX>
+static size_t lds_bytes_x2_t(const cs3d_plan p) {
+  const size_t a = (size_t)kTileJ * line_buf_elems<T, MX, 2>(p->d.nx) * sizeof(T);
+  const size_t b = (size_t)kTileJ * tile_stride(p->d.nx) * sizeof(T);
+  return (a > b ? a : b) + tw_bytes<T, MX>();
+}
+
 template <typename T, int MY, int WPL = default_wpl<MY>()>
 static size_t lds_bytes_y_t(const cs3d_plan p) {
   return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY, WPL>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
@@ -538,9 +581,24 @@ static int resident_blocks(KernelT kern, int threads, size_t lds, int ntiles) {
   return (int)(b < ntiles ? b : ntiles);
 }
 
+// resident_blocks after raising the kernel's dynamic LDS limit (the occupancy query needs it)
+template <typename KernelT>
+static int resident_blocks_at(KernelT kern, int threads, size_t lds, int ntiles) {
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return resident_blocks(kern, threads, lds, ntiles);
+}
+
 template <typename T, int MX, int KIND, typename TI>
 static hipError_t run_x_fwd_i(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
+  if constexpr (MX >= 512) {
+    if (p->tune.xwpl == 2) {  // two waves per line
+      const size_t lds = lds_bytes_x2_t<T, MX>(p);
+      const int nb = p->tune.xpersist ? resident_blocks_at(k_fwd_x2<T, MX, KIND, TI>, 128 * kTileJ, lds, ntiles) : ntiles;
+      return launch(k_fwd_x2<T, MX, KIND, TI>, dim3(nb), dim3(128 * kTileJ), lds, s, pd, ntiles);
+    }
+  }
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX, KIND, TI>),
@@ -560,6 +618,14 @@ static hipError_t run_x_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
 
 template <typename T, int MX, int KIND, bool ACC>
 static hipError_t run_x_inv_a(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (MX >= 512) {
+    if (p->tune.xwpl == 2) {  // two waves per line
+      const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
+      const size_t lds = lds_bytes_x2_t<T, MX>(p);
+      const int nb = p->tune.xpersist ? resident_blocks_at(k_inv_x2<T, MX, KIND, ACC>, 128 * kTileJ, lds, ntiles) : ntiles;
+      return launch(k_inv_x2<T, MX, KIND, ACC>, dim3(nb), dim3(128 * kTileJ), lds, s, pd, ntiles);
+    }
+  }
   const int ntiles = (p->ldy / kTileJ) * p->d.nz * nrhs;
   const size_t lds = lds_bytes_x_t<T, MX>(p);
   if (lds > 64 * 1024)
@@ -584,9 +650,9 @@ static dim3 y_grid(const cs3d_plan p, int nrhs) {
 
 // right-hand sides per y-pass workgroup: the tuned choice (1, 2 or 4), at most what the
 // register budget of the transform size allows
-template <typename T, int MY, int WPL, int NR, int KIND = kDst>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
 static hipError_t run_y_fwd_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
-  return launch(k_fwd_y<T, MY, WPL, NR, KIND>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
+  return launch(k_fwd_y<T, MY, WPL, NR, KIND, ROBIN>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
                 lds_bytes_y_t<T, MY, WPL>(p), s, pd, nrhs);
 }
 
@@ -602,8 +668,9 @@ static int y_rhs(const cs3d_plan p, int nrhs, int nrmax) {
   return nr;
 }
 
-template <typename T, int MY, int WPL, int KIND = kDst>
+template <typename T, int MY, int WPL, int KIND = kDst, bool ROBIN = false>
 static hipError_t run_y_fwd_w(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  if constexpr (ROBIN) return run_y_fwd_n<T, MY, WPL, 1, KIND, true>(p, pd, nrhs, s);  // one RHS per group
   if constexpr (YCfg<MY, WPL, KIND>::NRMAX >= 4) {
     const int nr = y_rhs(p, nrhs, 4);
     if (nr == 4) return run_y_fwd_n<T, MY, WPL, 4, KIND>(p, pd, nrhs, s);
@@ -623,12 +690,17 @@ static hipError_t run_y_back_w(const cs3d_plan p, const ProbDev& pd, int nrhs, h
 }
 
 // waves per y-line: the tuned choice where two are possible (M >= 512), else one
-template <typename T, int MY, int KIND = kDst>
+template <typename T, int MY, int KIND = kDst, bool ROBIN = false>
 static hipError_t run_y_fwd_t(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   if constexpr (MY >= 512) {
-    if (p->tune.ywpl == 2) return run_y_fwd_w<T, MY, 2, KIND>(p, pd, nrhs, s);
+    if (p->tune.ywpl == 2) return run_y_fwd_w<T, MY, 2, KIND, ROBIN>(p, pd, nrhs, s);
   }
-  return run_y_fwd_w<T, MY, 1, KIND>(p, pd, nrhs, s);
+  return run_y_fwd_w<T, MY, 1, KIND, ROBIN>(p, pd, nrhs, s);
+}
+// Robin z faces (FP64 sine transforms)
+template <typename T, int MY>
+static hipError_t run_y_fwd_robin(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  return run_y_fwd_t<T, MY, kDst, true>(p, pd, nrhs, s);
 }
 
 template <typename T, int MY, int KIND = kDst>
@@ -678,6 +750,7 @@ template <typename T>
 static hipError_t run_y_fwd(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
     if (p->neu) { CS3D_DISPATCH_DCT(run_y_fwd_t, p->fy, p, pd, nrhs, s) }
+    if (p->robin) { CS3D_DISPATCH(run_y_fwd_robin, p->fy, p, pd, nrhs, s) }
   }
   CS3D_DISPATCH(run_y_fwd_t, p->fy, p, pd, nrhs, s)
 }
@@ -698,14 +771,14 @@ static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStr
     hipLaunchKernelGGL(k_rhs_sides, grid, dim3(256), 0, s, pd);
     return hipGetLastError();
   }
-  const int nzc = (p->d.nz + pd.zchunk - 1) / pd.zchunk;
+  const int nzc = (pd.nz + pd.zchunk - 1) / pd.zchunk;
   dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreads), 0, s, pd);
   hipError_t e = hipGetLastError();
   // face corrections: x and y faces (6th order), z faces (6th order and the lift)
   const bool h6 = p->d.scheme == CS3D_HELM6;
-  const int nx = p->d.nx, ny = p->d.ny, nz = p->d.nz;
+  const int nx = p->d.nx, ny = p->d.ny, nz = pd.nz;
   for (int axis = 0; axis < 3 && e == hipSuccess; ++axis) {
     if (axis < 2 && !h6) continue;
     if (axis == 2 && !h6 && !pd.glo && !pd.ghi) continue;
@@ -714,6 +787,25 @@ static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStr
     e = hipGetLastError();
   }
   return e;
+}
+
+// Robin z faces: the interior planes z_1..z_N through the RHS pass of the physical grid (no
+// lift: the face data are not Dirichlet values), written from the second plane of u on, then
+// the rows of the two face planes (k_robin_faces)
+static hipError_t run_rhs_robin(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
+  ProbDev pi = pd;
+  pi.nz = p->nz_phys;
+  pi.u = pd.u + (long long)p->d.nx * p->d.ny;
+  pi.k2 = pd.k2 + 1;  // samples from z_0 on
+  pi.k2z = pd.k2z + 1;
+  pi.glo = pi.ghi = nullptr;
+  pi.robin = 0;
+  hipError_t e = run_rhs(p, pi, nrhs, s);
+  if (e != hipSuccess) return e;
+  const dim3 grid((p->d.nx * p->d.ny + 255) / 256, 2, nrhs);
+  if (grid.z > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_robin_faces, grid, dim3(256), 0, s, pd);
+  return hipGetLastError();
 }
 
 static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, const double* ghi,
@@ -745,7 +837,7 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.siny = p->dsiny;
   pd.f = f;
   const int cx = p->neu ? p->d.nx : p->d.nx + 2, cy = p->neu ? p->d.ny : p->d.ny + 2;  // closed grid
-  pd.f_stride = (long long)cx * cy * (p->d.nz + 2);
+  pd.f_stride = (long long)cx * cy * (p->robin ? p->d.nz : p->d.nz + 2);  // f: physical closed grid
   pd.glo = glo;
   pd.ghi = ghi;
   pd.g_stride = (long long)cx * cy;
@@ -757,6 +849,14 @@ static ProbDev make_pd(const cs3d_plan p, const double* f, const double* glo, co
   pd.C = p->ws ? reinterpret_cast<double*>(reinterpret_cast<char*>(p->ws) + off_C(p, nrhs)) : nullptr;
   pd.stats = p->dstats;
   pd.zchunk = p->tune.zchunk;
+  if (p->robin) {
+    pd.robin = 1;
+    for (int q = 0; q < 4; ++q) pd.rb[q] = p->rb[q];
+    for (int q = 0; q < 2; ++q) {
+      pd.ralpha[q] = p->d.robin_alpha[q];
+      pd.rbeta[q] = p->d.robin_beta[q];
+    }
+  }
   if (p->cplx) {
     pd.Wi = p->dWi;
     pd.LCi = p->dLCi;
@@ -898,7 +998,9 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   hipLaunchKernelGGL(k_stats_reset, dim3(1), dim3(64), 0, s, p->dstats);
   if (hipGetLastError() != hipSuccess) return CS3D_E_DEVICE;
   if (!assembled) {
-    if (mark(p, 0, s) != hipSuccess || run_rhs(p, pd, slots(p, nrhs), s) != hipSuccess) return CS3D_E_DEVICE;
+    if (mark(p, 0, s) != hipSuccess) return CS3D_E_DEVICE;
+    if ((p->robin ? run_rhs_robin(p, pd, nrhs, s) : run_rhs(p, pd, slots(p, nrhs), s)) != hipSuccess)
+      return CS3D_E_DEVICE;
     if (p->cplx && run_rhs_cx(p, pd, nrhs, s) != hipSuccess) return CS3D_E_DEVICE;
   }
   pd.u = u;
@@ -954,7 +1056,7 @@ extern "C" cs3d_status cs3d_residual(cs3d_plan p, int nrhs, const double* dev_f,
   if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
   if (!assembled && p->d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
   if (dev_r == dev_u || dev_r == dev_f) return CS3D_E_INVAL;
-  if (p->cplx || p->neu) return CS3D_E_UNSUPPORTED;
+  if (p->cplx || p->neu || p->robin) return CS3D_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)hip_stream;
   // F (with the lift) goes into r, then r = F - A U in place
   const ProbDev pd = make_pd(p, assembled ? nullptr : dev_f, dev_g_lo, dev_g_hi, nullptr, dev_r, nrhs);
@@ -1030,7 +1132,7 @@ extern "C" const char* cs3d_version(void) { return "cs3d 0.1 (gfx950)"; }
 static bool tuning_ok(const cs3d_tuning* t) {
   return t && t->zchunk >= 8 && t->zchunk <= 512 && (t->xpersist == 0 || t->xpersist == 1) &&
          (t->ywpl == 1 || t->ywpl == 2) && (t->order == 0 || t->order == 1) && (t->graph == 0 || t->graph == 1) &&
-         (t->yrhs == 1 || t->yrhs == 2 || t->yrhs == 4);
+         (t->yrhs == 1 || t->yrhs == 2 || t->yrhs == 4) && (t->xwpl == 1 || t->xwpl == 2);
 }
 
 static void tuning_out(const Tuning& t, cs3d_tuning* o) {
@@ -1040,6 +1142,7 @@ static void tuning_out(const Tuning& t, cs3d_tuning* o) {
   o->order = t.order;
   o->graph = t.graph;
   o->yrhs = t.yrhs;
+  o->xwpl = t.xwpl;
 }
 
 extern "C" cs3d_status cs3d_get_tuning(cs3d_plan p, cs3d_tuning* out) {
@@ -1054,6 +1157,7 @@ extern "C" cs3d_status cs3d_set_tuning(cs3d_plan p, const cs3d_tuning* t) {
   p->tune.xpersist = t->xpersist;
   p->tune.ywpl = t->ywpl;
   p->tune.yrhs = t->yrhs;
+  p->tune.xwpl = t->xwpl;
   return CS3D_OK;
 }
 
@@ -1088,6 +1192,7 @@ extern "C" cs3d_status cs3d_autotune(cs3d_plan p, int nrhs, const double* f, con
   std::vector<Axis> axes;
   axes.push_back({&Tuning::zchunk, {16, 32, 64, 128}, {0, 5}});
   axes.push_back({&Tuning::xpersist, {0, 1}, {1, 4}});
+  if (p->fx >= 512) axes.push_back({&Tuning::xwpl, {1, 2}, {1, 4}});
   if (p->fy >= 512) axes.push_back({&Tuning::ywpl, {1, 2}, {2, 3}});
   if (nrhs > 1) axes.push_back({&Tuning::yrhs, {1, 2, 4}, {2, 3}});
   for (const Axis& a : axes) {
@@ -1350,7 +1455,8 @@ extern "C" cs3d_status cs3d_batch_create(int n, const cs3d_desc* descs, void* hi
     const cs3d_status st = validate(&d);
     if (st != CS3D_OK) return st;
     if (d.scheme == CS3D_WEIGHTS) return CS3D_E_INVAL;
-    if (d.precision != CS3D_FP64 || d.k2_im || d.sides != CS3D_SIDES_DIRICHLET) return CS3D_E_UNSUPPORTED;
+    if (d.precision != CS3D_FP64 || d.k2_im || d.sides != CS3D_SIDES_DIRICHLET || d.zfaces != CS3D_ZFACES_DIRICHLET)
+      return CS3D_E_UNSUPPORTED;
   }
   cs3d_batch b = new (std::nothrow) cs3d_batch_s();
   if (!b) return CS3D_E_NOMEM;

@@ -75,6 +75,15 @@ struct ProbDev {
   const double* k2i;   // [nz+2] Im k^2
   const double* k2zi;  // [nz+2] Im (k^2)_z
   double* Ci;          // [nz][nx][ldy] Im c'
+  // Robin z faces: nz counts the system's planes z_0..z_{nz-1} (the face nodes are
+  // unknowns); the first and last modal rows take the ghost-plane elimination
+  //   row 0:    lambda^0 += (rb[0] + rb[1] mu) lambda^-,  lambda^+ += lambda^-
+  //   row nz-1: lambda^0 += (rb[2] + rb[3] mu) lambda^+,  lambda^- += lambda^+
+  // with mu = -2 s_n/hx^2 - 2 s_m/hy^2 the eigenvalue of the in-plane 5-point Laplacian;
+  // ralpha, rbeta: the conditions alpha u_z + beta u = g of the two faces
+  int robin;
+  double rb[4];
+  double ralpha[2], rbeta[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -223,8 +232,8 @@ __device__ __forceinline__ double face_corr(const ProbDev& p, int r, int i, int 
   }
   if (axis == 2) {
     // the weights through vector loads (an opaque offset): a uniform read here would
-    // otherwise become a scalar load, which can return what an earlier plan left at the
-    // same address
+    // otherwise become a scalar load, the kind of read under which plans created after
+    // others had been destroyed once gave wrong results (cause not isolated)
     const int o = opaque(0);
     if (l == 1 && p.glo) F -= plane9(p.W + o, p.glo + r * p.g_stride, p.nx, i, j);
     if (l == p.nz && p.ghi) F -= plane9(p.W + (p.nz - 1) * 12 + 8 + o, p.ghi + r * p.g_stride, p.nx, i, j);
@@ -472,6 +481,95 @@ __global__ void __launch_bounds__(256) k_rhs_faces(ProbDev p, int axis) {
 }
 
 // ---------------------------------------------------------------------------
+// Robin z faces: F on the face planes of the system (plane 0 at z_0, plane nz-1 at
+// z_{N+1}; p.nz counts the system's planes, f has p.nz closed-grid planes), one node per
+// thread:
+//  - the scheme's RHS operator at the face node (Sections 3.2-3.4) with the z differences
+//    one-sided into the box: delta_z^2 from (2, -5, 4, -1), delta_z^4 from
+//    (3, -14, 26, -24, 11, -2), delta_z from (-3, 4, -1)/2 (raw differences);
+//  - minus the face row's plane-offset weights applied to the data of the eliminated ghost
+//    plane, R = (s/alpha)((-2h + (h^3/3) k^2) g + (h^3/3) D g) - (h^3/3) f_z with s = +1 on
+//    the low face and -1 on the high face, D the in-plane 5-point Laplacian, f_z one-sided
+//    of second order (zero beyond the x/y sides, where g and u vanish).
+// grid: (ceil(nx ny / 256), 2 faces, right-hand sides)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_robin_faces(ProbDev p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= p.nx * p.ny) return;
+  const int i = 1 + e % p.nx, j = 1 + e / p.nx;
+  const int face = blockIdx.y, r = blockIdx.z;
+  const long long sy = p.nx + 2, sz = sy * (p.ny + 2);
+  const double* f = p.f + r * p.f_stride;
+  const double sg = face ? -1.0 : 1.0;
+  // plane q of f counted from the face into the box (q = 0: the face plane)
+  auto fp = [&](int q) -> const double* { return f + sz * (face ? p.nz - 1 - q : q); };
+  auto at = [&](const double* P, int ii, int jj) -> double { return P[ii + sy * jj]; };
+  const double* f0 = fp(0);
+  const double* f1 = fp(1);
+  const double* f2 = fp(2);
+  const double* f3 = fp(3);
+  // one-sided second z difference (raw) at an in-plane node
+  auto d2z = [&](int ii, int jj) -> double {
+    return 2.0 * at(f0, ii, jj) - 5.0 * at(f1, ii, jj) + 4.0 * at(f2, ii, jj) - at(f3, ii, jj);
+  };
+  const double h = p.hz, h2 = h * h, h3 = h2 * h;
+  const double c0 = at(f0, i, j);
+  const double d2x = at(f0, i - 1, j) - 2.0 * c0 + at(f0, i + 1, j);
+  const double d2y = at(f0, i, j - 1) - 2.0 * c0 + at(f0, i, j + 1);
+  const double dzz = d2z(i, j);
+  // sample index of the face plane: z_0 at 1, z_{N+1} at p.nz (samples from z_{-1})
+  const int ks = face ? p.nz : 1;
+  const double k2f = p.k2[ks], k2zf = p.k2z[ks];
+  double F;
+  if (p.scheme == kHelm2) {
+    F = h2 * c0;
+  } else if (p.scheme == kHelm4) {
+    F = h2 * (c0 + (d2x + d2y + dzz) / 12.0);
+  } else {
+    // 6th order (uniform h): fourth differences in x and y with the one-sided formula on
+    // the first and last interior lines, as in the interior planes
+    const double* cc = f0 + i + sy * j;
+    const double d4x = (i == 1 || i == p.nx) ? d4_onesided(cc, 1, i == 1)
+                                             : cc[-2] - 4.0 * (cc[-1] + cc[1]) + 6.0 * cc[0] + cc[2];
+    const double d4y = (j == 1 || j == p.ny) ? d4_onesided(cc, sy, j == 1)
+                                             : cc[-2 * sy] - 4.0 * (cc[-sy] + cc[sy]) + 6.0 * cc[0] + cc[2 * sy];
+    const double d4z = 3.0 * c0 - 14.0 * at(f1, i, j) + 26.0 * at(f2, i, j) - 24.0 * at(f3, i, j) +
+                       11.0 * at(fp(4), i, j) - 2.0 * at(fp(5), i, j);
+    const double d2xy = (at(f0, i - 1, j - 1) - 2.0 * at(f0, i, j - 1) + at(f0, i + 1, j - 1)) -
+                        2.0 * d2x + (at(f0, i - 1, j + 1) - 2.0 * at(f0, i, j + 1) + at(f0, i + 1, j + 1));
+    const double d2xz = d2z(i - 1, j) - 2.0 * dzz + d2z(i + 1, j);
+    const double d2yz = d2z(i, j - 1) - 2.0 * dzz + d2z(i, j + 1);
+    const double d1z = sg * (-3.0 * c0 + 4.0 * at(f1, i, j) - at(f2, i, j)) * 0.5;
+    F = h2 * (c0 + (d2x + d2y + dzz) / 12.0 - (d4x + d4y + d4z) / 240.0 + (d2xy + d2xz + d2yz) / 90.0 -
+              h2 * k2f * c0 / 20.0 + h3 * k2zf * d1z / 60.0);
+  }
+  // the ghost-plane data R at an interior in-plane node (zero beyond the sides)
+  const double* g = face ? p.ghi : p.glo;
+  const double* gr = g ? g + r * p.g_stride : nullptr;
+  const double ia = 1.0 / p.ralpha[face];
+  const double cg = -2.0 * h + (h3 / 3.0) * k2f;
+  auto R = [&](int ii, int jj) -> double {
+    if (ii < 1 || ii > p.nx || jj < 1 || jj > p.ny) return 0.0;
+    double v = 0.0;
+    if (gr) {
+      const double gc = at(gr, ii, jj);
+      const double lap = (at(gr, ii - 1, jj) - 2.0 * gc + at(gr, ii + 1, jj)) / (p.hx * p.hx) +
+                         (at(gr, ii, jj - 1) - 2.0 * gc + at(gr, ii, jj + 1)) / (p.hy * p.hy);
+      v = sg * ia * (cg * gc + (h3 / 3.0) * lap);
+    }
+    const double fz = (-3.0 * at(f0, ii, jj) + 4.0 * at(f1, ii, jj) - at(f2, ii, jj)) / (2.0 * h);
+    return v - (h3 / 3.0) * fz;
+  };
+  // the face row's weights of the ghost side: row 0 offset -1, row nz-1 offset +1
+  const int o = opaque(0);
+  const double* w = p.W + (face ? (long long)(p.nz - 1) * 12 + 8 : 0) + o;
+  const double lift = w[0] * (R(i - 1, j - 1) + R(i + 1, j - 1) + R(i - 1, j + 1) + R(i + 1, j + 1)) +
+                      w[1] * (R(i - 1, j) + R(i + 1, j)) + w[2] * (R(i, j - 1) + R(i, j + 1)) + w[3] * R(i, j);
+  p.u[r * p.u_stride + (long long)(face ? p.nz - 1 : 0) * p.nx * p.ny + (i - 1) + (long long)p.nx * (j - 1)] =
+      F - lift;
+}
+
+// ---------------------------------------------------------------------------
 // RHS operator for Neumann sides: p.nx, p.ny count the nodes of an x/y plane (the
 // side nodes are unknowns), f is the closed grid with rows of p.nx values, and a
 // value beyond a side is the mirror image about it (f_{-1} = f_1, f_{-2} = f_2).
@@ -674,8 +772,91 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
 }
 
 // ---------------------------------------------------------------------------
+// K1 with two wavefronts per x-line (FFT lengths 512 and 1024): the same tiles of kTileJ
+// y-lines, layout, transpose and stores as k_fwd_x, with 1024 threads per workgroup and
+// half the values of a line per lane.  The registers of a lane then fit four waves per
+// SIMD (one workgroup per CU: the LDS of the line buffers).  Every line of a workgroup
+// runs the transform (its exchanges synchronise the workgroup); lines past N_y transform
+// zeros and store zeros.
+// ---------------------------------------------------------------------------
+constexpr int kNV2 = 8;  // ceil(1023/128): row values per lane
+
+template <typename T, int MX, int KIND = kDst, typename TI = double>
+__global__ void __launch_bounds__(128 * kTileJ) k_fwd_x2(ProbDev p, int ntiles) {
+  static_assert(MX >= 512, "two waves per line need M >= 512");
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  constexpr int NS = Tx<MX, 2, KIND>::NS;
+  const int w = threadIdx.x >> 7, tl = threadIdx.x & 127;
+  const int bufn = line_buf_elems<T, MX, 2>(p.nx);
+  const int ts = tile_stride(p.nx);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  load_twiddles<T, MX, 2>(tab, p.twx);
+  T* buf = smem + w * bufn;
+  TI pre[kNV2];
+  auto fetch = [&](int t) {
+    const XTile x = decode_xtile(p, t, w);
+    const int ln = opaque(tl);
+    const TI* Fr = reinterpret_cast<const TI*>(p.F) + x.r * p.u_stride +
+                   (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1)) + ln;
+#pragma unroll
+    for (int k = 0; k < kNV2; ++k) pre[k] = (x.active && ln + 128 * k < p.nx) ? Fr[128 * k] : (TI)0;
+  };
+  int t = xcd_order(blockIdx.x, gridDim.x);
+  if (t < ntiles) fetch(t);
+  settle(pre);
+  for (; t < ntiles; t += gridDim.x) {
+    const XTile x = decode_xtile(p, t, w);
+    __syncthreads();  // the previous tile's store phase is done with the LDS
+    if (tl == 0) buf[0] = (T)0;
+#pragma unroll
+    for (int k = 0; k < kNV2; ++k) {
+      const int i = 1 + tl + 128 * k;
+      if (i <= p.nx) buf[i] = (T)pre[k];  // zeros for a line past N_y
+    }
+    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
+    __syncthreads();  // also publishes the twiddle table on the first pass
+    T out[NS];
+    line_dst<T, MX, 2, false, KIND>(buf, p.nx, out, tl, tab, p.sinx);
+    __syncthreads();
+    // tile[jj][n], n = 1..nx
+    if (x.active) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int n = line_mode<MX, 2, KIND>(tl, s, p.nx);
+        if (n > 0) smem[w * ts + n] = out[s];
+      }
+    } else {
+      for (int n = 1 + tl; n <= p.nx; n += 128) smem[w * ts + n] = (T)0;
+    }
+    __syncthreads();
+    settle(pre);  // the next tile's rows, fetched before the transform
+    T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
+    for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
+      const int n0 = idx / kTileJ, jj = idx % kTileJ;
+      G[(long long)n0 * p.ldy + jj] = smem[jj * ts + n0 + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K2: DST along y + modal eigenvalues + forward elimination.
 // ---------------------------------------------------------------------------
+// Robin z faces: the first and last rows of a modal system (plane l of 1..nz) after the
+// elimination of the ghost planes (the face rows of the system's first and last plane)
+__device__ __forceinline__ void robin_rows(const ProbDev& p, int l, double sn, double sm, double& lm,
+                                           double& l0, double& lp) {
+  const double mu = -2.0 * sn / (p.hx * p.hx) - 2.0 * sm / (p.hy * p.hy);
+  if (l == 1) {
+    l0 += (p.rb[0] + p.rb[1] * mu) * lm;
+    lp += lm;
+  }
+  if (l == p.nz) {
+    l0 += (p.rb[2] + p.rb[3] * mu) * lp;
+    lm += lp;
+  }
+}
+
 __device__ __forceinline__ void record_pivot(double piv, double& minpiv, unsigned& bad) {
   const double a = fabs(piv);
   if (!(a > 0.0) || !isfinite(a)) {
@@ -734,7 +915,8 @@ __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load)
 // every mode are formed with the first of them and applied to all (the LU of Section
 // 3.6 does not depend on the right-hand side).  The workgroup of r0 = 0 stores c' and
 // records the pivots.
-template <typename T, int MY, int WPL, int NR, int KIND = kDst>
+// ROBIN: Robin z faces, whose first and last modal rows change (robin_rows)
+template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
 __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL, KIND>;
   constexpr int NS = C::NS;
@@ -822,7 +1004,8 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
             const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
             const bool valid = active && m > 0;
             const double sm = smv[s];
-            const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+            double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+            if constexpr (ROBIN) robin_rows(p, l, ctn, sm, lm, l0, lpv);
             const double piv = l0 - lm * cp[s];
             if (lead && valid) record_pivot(piv, minpiv, bad);
             inv[s] = 1.0 / piv;
@@ -836,7 +1019,8 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
             const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
             if (m > 0) {
               const double sm = p.cty[m - 1];
-              const double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+              double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+              if constexpr (ROBIN) robin_rows(p, l, ctn, sm, lm, l0, lpv);
               const double piv = l0 - lm * cp[s];
               if (lead) record_pivot(piv, minpiv, bad);
               inv[s] = 1.0 / piv;
@@ -872,13 +1056,13 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
 }
 
 // grid: (line groups, groups of NR right-hand sides)
-template <typename T, int MY, int WPL, int NR, int KIND = kDst>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
 __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
   const int r0 = blockIdx.y * NR;
-  yfwd_block<T, MY, WPL, NR, KIND>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
+  yfwd_block<T, MY, WPL, NR, KIND, ROBIN>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,6 +1248,94 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int i = line_mode<MX, 1, KIND>(lane, s, p.nx);
+        if constexpr (FIXED) {
+          // the one slot without a mode (lane 0, mode 0) writes u[0] with the value of its
+          // own slot 1 (mode 1), which stores it too
+          u[i > 0 ? i - 1 : 0] = p.scale * (double)(i > 0 ? out[s] : out[1]);
+        } else if constexpr (ACC) {
+          if (i > 0) u[i - 1] = u[i - 1] + p.scale * (double)out[s];
+        } else {
+          if (i > 0) u[i - 1] = p.scale * (double)out[s];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4 with two wavefronts per x-line (FFT lengths 512 and 1024): the tiles, transposes and
+// stores of k_inv_x with 1024 threads per workgroup and half a line per lane.  Every line
+// runs the transform (lines past N_y hold the zeros K1 stored there and store nothing).
+// ---------------------------------------------------------------------------
+template <typename T, int MX, int KIND = kDst, bool ACC = false>
+__global__ void __launch_bounds__(128 * kTileJ) k_inv_x2(ProbDev p, int ntiles) {
+  static_assert(MX >= 512, "two waves per line need M >= 512");
+  extern __shared__ double smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  constexpr int NS = Tx<MX, 2, KIND>::NS;
+  constexpr int XR = 128;  // tile rows one pass of the workgroup covers
+  constexpr bool FIXED = KIND == kDst && !ACC;
+  constexpr int NT = FIXED ? MX / XR : (1023 + XR - 1) / XR;  // values per thread
+  const int w = threadIdx.x >> 7, tl = threadIdx.x & 127;
+  const int bufn = line_buf_elems<T, MX, 2>(p.nx);
+  const int ts = tile_stride(p.nx);
+  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  load_twiddles<T, MX, 2>(tab, p.twx);
+  T* buf = smem + w * bufn;
+  T pre[NT];
+  // thread (n0, jj) moves rows n0, n0 + 128, ... of column jj of the tile (offsets rebuilt
+  // per tile from an opaque thread index)
+  auto fetch = [&](int t) {
+    const XTile x = decode_xtile(p, t, 0);
+    const int tid = opaque((int)threadIdx.x);
+    const int n0 = tid / kTileJ, jj = tid % kTileJ;
+    if constexpr (FIXED) {
+      const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
+                   x.jt * kTileJ + jj;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const int row = n0 + XR * k;
+        pre[k] = G[(long long)opaque(row < p.nx ? row : 0) * p.ldy];  // row M - 1: a valid stand-in
+      }
+    } else {
+      const T* G = reinterpret_cast<const T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy +
+                   x.jt * kTileJ + (long long)n0 * p.ldy + jj;
+      const long long step = (long long)XR * p.ldy;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) pre[k] = (n0 + XR * k < p.nx) ? G[k * step] : (T)0;
+    }
+  };
+  int t = xcd_order(blockIdx.x, gridDim.x);
+  if (t < ntiles) fetch(t);
+  settle(pre);
+  for (; t < ntiles; t += gridDim.x) {
+    const XTile x = decode_xtile(p, t, w);
+    __syncthreads();  // the previous transform is done with the LDS
+    {
+      const int tid = opaque((int)threadIdx.x);
+      const int n0 = tid / kTileJ, jj = tid % kTileJ;
+      T* row = smem + jj * ts + n0 + 1;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if constexpr (FIXED) {
+          row[XR * k] = pre[k];  // position M of the tile row is not read by the transform
+        } else {
+          if (n0 + XR * k < p.nx) row[XR * k] = pre[k];
+        }
+      }
+    }
+    __syncthreads();  // also publishes the twiddle table on the first pass
+    if (t + (int)gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the transform
+    // the transform reads its input straight from tile row w; the workgroup barrier
+    // inside separates those reads from the exchanges that overlay the tile
+    T out[NS];
+    line_dst<T, MX, 2, true, KIND>(buf, p.nx, out, tl, tab, p.sinx, smem + w * ts);
+    settle(pre);  // the next tile's segments, fetched before the transform
+    if (x.active) {
+      double* u = p.u + x.r * p.u_stride + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int i = line_mode<MX, 2, KIND>(tl, s, p.nx);
         if constexpr (FIXED) {
           // the one slot without a mode (lane 0, mode 0) writes u[0] with the value of its
           // own slot 1 (mode 1), which stores it too

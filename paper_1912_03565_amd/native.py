@@ -43,6 +43,9 @@ class Desc(ctypes.Structure):
         ("k2_z_im", ctypes.POINTER(ctypes.c_double)),
         ("k2_zz_im", ctypes.POINTER(ctypes.c_double)),
         ("sides", ctypes.c_int),
+        ("zfaces", ctypes.c_int),
+        ("robin_alpha", ctypes.c_double * 2),
+        ("robin_beta", ctypes.c_double * 2),
     ]
 
 
@@ -63,6 +66,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("zchunk", ctypes.c_int), ("xpersist", ctypes.c_int), ("ywpl", ctypes.c_int),
         ("order", ctypes.c_int), ("graph", ctypes.c_int), ("yrhs", ctypes.c_int),
+        ("xwpl", ctypes.c_int),
     ]
 
     def as_dict(self):

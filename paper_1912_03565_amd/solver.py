@@ -50,8 +50,12 @@ SIDES = {"dirichlet": 0, "neumann": 1}
 
 
 def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, gamma=0.0,
-               weights=None, precision="fp64", refine_steps=2, max_rhs=1, sides="dirichlet"):
-    """cs3d_desc and the host arrays it points to (keep them alive during the call)."""
+               weights=None, precision="fp64", refine_steps=2, max_rhs=1, sides="dirichlet",
+               robin=None):
+    """cs3d_desc and the host arrays it points to (keep them alive during the call).
+
+    robin: None (Dirichlet z faces) or ((alpha_lo, alpha_hi), (beta_lo, beta_hi)); the k^2
+    samples then cover z_{-1}..z_{nz+2} (nz + 4 values)."""
     keep = []
     d = N.Desc()
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
@@ -59,7 +63,8 @@ def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, g
     d.scheme = N.SCHEMES[scheme]
     # complex k (absorbing media): real parts in k2..., imaginary parts in k2..._im
     cplx = k2 is not None and np.iscomplexobj(np.asarray(k2))
-    fields = [("k2", k2, nz + 2), ("k2_z", k2_z, nz + 2), ("k2_zz", k2_zz, nz + 2), ("weights", weights, nz * 12)]
+    nks = nz + (4 if robin is not None else 2)
+    fields = [("k2", k2, nks), ("k2_z", k2_z, nks), ("k2_zz", k2_zz, nks), ("weights", weights, nz * 12)]
     if cplx:
         fields = [(nm, None if arr is None else np.real(np.asarray(arr)), n) for nm, arr, n in fields[:3]]
         fields += [(nm + "_im", None if arr is None else np.imag(np.asarray(arr)), nz + 2)
@@ -75,6 +80,11 @@ def _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None, g
     d.refine_steps = int(refine_steps)
     d.max_rhs = int(max_rhs)
     d.sides = SIDES[sides]
+    if robin is not None:
+        (a0, a1), (b0, b1) = robin
+        d.zfaces = 1
+        d.robin_alpha[0], d.robin_alpha[1] = float(a0), float(a1)
+        d.robin_beta[0], d.robin_beta[1] = float(b0), float(b1)
     return d, keep
 
 
@@ -83,8 +93,10 @@ class Plan:
 
     def __init__(self, nx, ny, nz, hx, hy, hz, scheme, k2=None, k2_z=None, k2_zz=None,
                  gamma=0.0, weights=None, precision="fp64", refine_steps=2, max_rhs=1,
-                 device="cuda", stream=None, sides="dirichlet"):
+                 device="cuda", stream=None, sides="dirichlet", robin=None):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        # Robin z faces: the z-face nodes are unknowns, a solution holds nz + 2 planes
+        self.robin = robin
         # Neumann sides: the side nodes are unknowns, a solution plane has (ny+2) x (nx+2) nodes
         self.sides = sides
         self.scheme = scheme
@@ -94,7 +106,7 @@ class Plan:
         self.max_rhs = int(max_rhs)
         self.device = torch.device(device)
         d, keep = _make_desc(nx, ny, nz, hx, hy, hz, scheme, k2, k2_z, k2_zz, gamma, weights,
-                             precision, refine_steps, max_rhs, sides)
+                             precision, refine_steps, max_rhs, sides, robin)
         self._plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             N.check("cs3d_plan_create",
@@ -113,6 +125,8 @@ class Plan:
     def interior_shape(self, nrhs):
         if self.sides == "neumann":
             return self._lead(nrhs) + (self.nz, self.ny + 2, self.nx + 2)
+        if self.robin is not None:
+            return self._lead(nrhs) + (self.nz + 2, self.ny, self.nx)
         return self._lead(nrhs) + (self.nz, self.ny, self.nx)
 
     def plane_shape(self, nrhs):
@@ -232,11 +246,13 @@ class Plan:
 
 def plan_for_problem(p, precision="fp64", refine_steps=2, max_rhs=None, device="cuda", weights=None):
     """Plan matching a workloads.Problem description."""
+    robin = getattr(p, "robin", None)
     return Plan(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, p.scheme if weights is None else "weights",
-                k2=p.k2, k2_z=p.k2_z if p.scheme == "helm6" else None,
+                k2=p.k2, k2_z=p.k2_z if (p.scheme == "helm6" or robin is not None) else None,
                 k2_zz=p.k2_zz if p.scheme == "helm6" else None, gamma=p.gamma, weights=weights,
                 precision=precision, refine_steps=refine_steps,
-                max_rhs=max_rhs or p.nrhs, device=device, sides=getattr(p, "sides", "dirichlet"))
+                max_rhs=max_rhs or p.nrhs, device=device, sides=getattr(p, "sides", "dirichlet"),
+                robin=robin)
 
 
 class Batch:
