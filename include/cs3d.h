@@ -66,7 +66,8 @@ typedef enum {
   CS3D_E_SINGULAR = 4,       /* a zero or non-finite pivot was met (from cs3d_get_stats) */
   CS3D_E_NOTCONVERGED = 5,   /* refinement did not reach its residual target */
   CS3D_E_UNSUPPORTED = 6,    /* valid request this build cannot serve */
-  CS3D_E_WORKSPACE = 7       /* workspace missing or too small */
+  CS3D_E_WORKSPACE = 7,      /* workspace missing or too small */
+  CS3D_E_TOO_LARGE = 8       /* cs3d_solve_static: the solve needs more than its scratch */
 } cs3d_status;
 
 typedef enum {
@@ -196,6 +197,22 @@ cs3d_status cs3d_set_workspace(cs3d_plan plan, void* dev_workspace, size_t bytes
  * no RHS operator - use cs3d_solve_assembled), E_WORKSPACE, E_DEVICE. */
 cs3d_status cs3d_solve(cs3d_plan plan, int nrhs, const double* dev_f, const double* dev_g_lo,
                        const double* dev_g_hi, double* dev_u, void* hip_stream);
+
+/* cs3d_solve for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same passes as cs3d_solve, with the
+ * workspace in a static device array of CS3D_STATIC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends (the plan's own workspace, if set, is not
+ * used or touched).  Call with the plan's device current.  No per-pass timing is recorded
+ * (cs3d_get_stats still reports pivots, residuals and the solve time).  Nothing is
+ * allocated: no hipMalloc/hipFree, no events, no library allocations.
+ * Every call on one device shares that device's scratch: calls that overlap on a device
+ * (other streams, other host threads, other plans) race and must be ordered by the caller.
+ * The scratch keeps the last call's contents; no pass reads it before writing it.
+ * Errors: as cs3d_solve, plus E_TOO_LARGE when cs3d_workspace_bytes(plan, nrhs) exceeds
+ * CS3D_STATIC_SCRATCH_BYTES (64 MiB: for instance one FP64 right-hand side up to about 159^3). */
+#define CS3D_STATIC_SCRATCH_BYTES (64u << 20)
+cs3d_status cs3d_solve_static(cs3d_plan plan, int nrhs, const double* dev_f, const double* dev_g_lo,
+                              const double* dev_g_hi, double* dev_u, void* hip_stream);
 
 /* Solve A U = F for an interior right-hand side F already assembled by the caller
  * (any scheme; z-face data, if any, already lifted).  dev_F and dev_u are interior arrays.

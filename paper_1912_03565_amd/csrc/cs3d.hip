@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -78,6 +79,7 @@ struct cs3d_plan_s {
   hipStream_t last_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  bool notime = false;  // a cs3d_solve_static call: no per-pass timing (its ring would need events)
   // Robin z faces: d.nz counts the system's planes (nz + 2), nz_phys the interior ones
   bool robin = false;
   int nz_phys = 0;
@@ -883,6 +885,7 @@ static hipError_t ensure_ring(cs3d_plan p) {
 
 // Interval timing: mark(stage) starts an interval of that stage, end_solve closes the last.
 static hipError_t mark(cs3d_plan p, int stage, hipStream_t s) {
+  if (p->notime) return hipSuccess;
   if (p->cur_marks >= kMaxMarks) return hipSuccess;  // further passes are not timed separately
   const size_t q = (size_t)(p->solves % kRing);
   p->ring_sid[q * kMaxMarks + p->cur_marks] = (signed char)stage;
@@ -890,6 +893,7 @@ static hipError_t mark(cs3d_plan p, int stage, hipStream_t s) {
 }
 
 static hipError_t end_solve(cs3d_plan p, hipStream_t s) {
+  if (p->notime) return hipSuccess;
   const size_t q = (size_t)(p->solves % kRing);
   const hipError_t e = hipEventRecord(p->ring[q * (kMaxMarks + 1) + p->cur_marks], s);
   p->ring_n[q] = p->cur_marks;
@@ -983,7 +987,7 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
   if (!p->ws || p->ws_bytes < cs3d_workspace_bytes(p, nrhs)) return CS3D_E_WORKSPACE;
   if (assembled && f == u) return CS3D_E_INVAL;  // F must stay intact until K1 has read all of it
   hipStream_t s = (hipStream_t)hip_stream;
-  if (ensure_ring(p) != hipSuccess) return CS3D_E_DEVICE;
+  if (!p->notime && ensure_ring(p) != hipSuccess) return CS3D_E_DEVICE;
   p->last_stream = s;
   p->cur_marks = 0;
   const bool mixed = p->d.precision != CS3D_FP64;
@@ -1042,6 +1046,60 @@ static cs3d_status solve_common(cs3d_plan p, int nrhs, const double* f, int asse
 extern "C" cs3d_status cs3d_solve(cs3d_plan p, int nrhs, const double* dev_f, const double* dev_g_lo,
                                   const double* dev_g_hi, double* dev_u, void* hip_stream) {
   return solve_common(p, nrhs, dev_f, 0, dev_g_lo, dev_g_hi, dev_u, hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch for callers that cannot allocate (cs3d_solve_static).  Every device the
+// library runs on holds its own copy of the array until the process ends.  In host code
+// the array's name is only a stand-in: its address on a device comes from
+// hipGetSymbolAddress with that device current, taken once per device and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char cs3d_scratch[CS3D_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+cs3d_status static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return CS3D_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(cs3d_scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return CS3D_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CS3D_OK;
+}
+}  // namespace
+
+extern "C" cs3d_status cs3d_solve_static(cs3d_plan p, int nrhs, const double* dev_f, const double* dev_g_lo,
+                                         const double* dev_g_hi, double* dev_u, void* hip_stream) {
+  if (!p) return CS3D_E_INVAL;
+  if (nrhs < 1 || nrhs > p->d.max_rhs) return CS3D_E_INVAL;
+  if (cs3d_workspace_bytes(p, nrhs) > (size_t)CS3D_STATIC_SCRATCH_BYTES) return CS3D_E_TOO_LARGE;
+  void* scratch = nullptr;
+  const cs3d_status got = static_scratch(&scratch);
+  if (got != CS3D_OK) return got;
+  // the plan's own workspace (if any) is left alone; the kernels take the scratch address
+  void* const ws = p->ws;
+  const size_t ws_bytes = p->ws_bytes;
+  p->ws = scratch;
+  p->ws_bytes = (size_t)CS3D_STATIC_SCRATCH_BYTES;
+  p->notime = true;
+  const cs3d_status st = solve_common(p, nrhs, dev_f, 0, dev_g_lo, dev_g_hi, dev_u, hip_stream);
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  p->notime = false;
+  return st;
 }
 
 extern "C" cs3d_status cs3d_solve_assembled(cs3d_plan p, int nrhs, const double* dev_F, double* dev_u,
@@ -1119,6 +1177,7 @@ extern "C" const char* cs3d_status_str(cs3d_status st) {
     case CS3D_E_NOTCONVERGED: return "refinement did not converge";
     case CS3D_E_UNSUPPORTED: return "unsupported request";
     case CS3D_E_WORKSPACE: return "workspace missing or too small";
+    case CS3D_E_TOO_LARGE: return "problem needs more scratch than cs3d_solve_static holds";
     default: return "unknown status";
   }
 }

@@ -21,6 +21,7 @@ E_SINGULAR = 4
 E_NOTCONVERGED = 5
 E_UNSUPPORTED = 6
 E_WORKSPACE = 7
+E_TOO_LARGE = 8
 
 SCHEMES = {"helm2": 2, "helm4": 4, "helm6": 6, "cd4": 14, "weights": 99}
 PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_fp32": 1}
@@ -82,7 +83,7 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = [
     "cs3d_plan_create", "cs3d_plan_destroy", "cs3d_workspace_bytes", "cs3d_set_workspace",
-    "cs3d_solve", "cs3d_solve_assembled", "cs3d_residual", "cs3d_get_stats",
+    "cs3d_solve", "cs3d_solve_static", "cs3d_solve_assembled", "cs3d_residual", "cs3d_get_stats",
     "cs3d_batch_create", "cs3d_batch_workspace_bytes", "cs3d_batch_set_workspace",
     "cs3d_batch_solve", "cs3d_batch_get_stats", "cs3d_batch_destroy", "cs3d_status_str",
     "cs3d_version", "cs3d_reset_timers", "cs3d_get_tuning", "cs3d_set_tuning", "cs3d_autotune",
@@ -107,6 +108,7 @@ def _load():
         "cs3d_workspace_bytes": (sz, [vp, i]),
         "cs3d_set_workspace": (i, [vp, vp, sz]),
         "cs3d_solve": (i, [vp, i, dp, dp, dp, dp, vp]),
+        "cs3d_solve_static": (i, [vp, i, dp, dp, dp, dp, vp]),
         "cs3d_solve_assembled": (i, [vp, i, dp, dp, vp]),
         "cs3d_residual": (i, [vp, i, dp, i, dp, dp, dp, dp, vp]),
         "cs3d_get_stats": (i, [vp, ctypes.POINTER(Stats)]),
