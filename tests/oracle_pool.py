@@ -112,13 +112,23 @@ def workers():
     return max(1, min(16, n))
 
 
+def _indexed(args):
+    fn, i, item = args
+    return i, fn(item)
+
+
 def _run(fn, items, nproc):
     saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
     for k in saved:
         os.environ[k] = "1"
     try:
+        out = [None] * len(items)
         with mp.get_context("spawn").Pool(nproc) as pool:
-            return pool.map(fn, items, chunksize=1)
+            # one line per finished item, so a long pool run keeps printing
+            for k, (i, r) in enumerate(pool.imap_unordered(_indexed, [(fn, i, it) for i, it in enumerate(items)])):
+                out[i] = r
+                print(f"    oracle jobs: {k + 1} of {len(items)} done", flush=True)
+        return out
     finally:
         for k, v in saved.items():
             if v is None:

@@ -101,6 +101,7 @@ def test_batch_general_variant_matches_oracle(cs3d):
     b.close()
 
 
+@pytest.mark.timeout(900)  # host oracle work in worker processes
 def test_batch_of_64_uneven_problems(cs3d):
     """64 problems, per-axis sizes drawn from {63, 127, 255}, HELM4/HELM6/CD4 in turn with
     k0 ~ U[5, 60] or gamma ~ U[-100, -5], solved in one batch.
