@@ -178,9 +178,9 @@ __device__ __forceinline__ void xinv_item(const ProbDev& p, int t, T* lines, con
 
 template <typename T, int MAXM, bool DENSE, bool FWD>
 __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tab = lds_table(smem);
   T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
   int curM = -1;
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
@@ -209,9 +209,9 @@ __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
 // ---------------------------------------------------------------------------
 template <typename T, int MAXM, bool DENSE, bool FWD>
 __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tab = lds_table(smem);
   T* lines = smem + (size_t)tw_entries<MAXM>() * sizeof(cx<T>) / sizeof(T);
   int curM = -1;
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {

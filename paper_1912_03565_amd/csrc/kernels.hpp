@@ -716,13 +716,13 @@ __device__ __forceinline__ XTile decode_xtile(const ProbDev& p, int t, int w) {
 // TI: element type of the input p.F (FP32 for the residuals of the mixed path)
 template <typename T, int MX, int KIND = kDst, typename TI = double>
 __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 1, KIND>::NS;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  cx<T>* tab = lds_table(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
   TI pre[kNV];
@@ -784,13 +784,13 @@ constexpr int kNV2 = 8;  // ceil(1023/128): row values per lane
 template <typename T, int MX, int KIND = kDst, typename TI = double>
 __global__ void __launch_bounds__(128 * kTileJ) k_fwd_x2(ProbDev p, int ntiles) {
   static_assert(MX >= 512, "two waves per line need M >= 512");
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 2, KIND>::NS;
   const int w = threadIdx.x >> 7, tl = threadIdx.x & 127;
   const int bufn = line_buf_elems<T, MX, 2>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  cx<T>* tab = lds_table(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   load_twiddles<T, MX, 2>(tab, p.twx);
   T* buf = smem + w * bufn;
   TI pre[kNV2];
@@ -901,7 +901,7 @@ struct YCfg {
 template <typename T, int MY, int WPL>
 __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load) {
   const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + YCfg<MY, WPL>::LPB * bufn);
+  cx<T>* tab = lds_table(smem + YCfg<MY, WPL>::LPB * bufn);
   if constexpr (MY != 0) {
     if (load) load_twiddles<T, MY, WPL>(tab, p.twy);
   }
@@ -1058,7 +1058,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
 // grid: (line groups, groups of NR right-hand sides)
 template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
 __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
   const int r0 = blockIdx.y * NR;
@@ -1158,7 +1158,7 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
 
 template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
   const int r0 = blockIdx.y * NR;
@@ -1179,7 +1179,7 @@ constexpr bool kInvPrefetch = CS3D_INV_PREFETCH != 0;
 // ACC: u += the result (refinement corrections) instead of u = the result
 template <typename T, int MX, int KIND = kDst, bool ACC = false>
 __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 1, KIND>::NS;
   // FIXED: as in k_fwd_x, a fixed number of loads and stores per lane and tile (sine FFT of
@@ -1189,7 +1189,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  cx<T>* tab = lds_table(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   if constexpr (MX != 0) load_twiddles<T, MX, 1>(tab, p.twx);
   T* buf = smem + w * bufn;
   T pre[NT];
@@ -1270,7 +1270,7 @@ __global__ void __launch_bounds__(64 * kTileJ) k_inv_x(ProbDev p, int ntiles) {
 template <typename T, int MX, int KIND = kDst, bool ACC = false>
 __global__ void __launch_bounds__(128 * kTileJ) k_inv_x2(ProbDev p, int ntiles) {
   static_assert(MX >= 512, "two waves per line need M >= 512");
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int NS = Tx<MX, 2, KIND>::NS;
   constexpr int XR = 128;  // tile rows one pass of the workgroup covers
@@ -1279,7 +1279,7 @@ __global__ void __launch_bounds__(128 * kTileJ) k_inv_x2(ProbDev p, int ntiles) 
   const int w = threadIdx.x >> 7, tl = threadIdx.x & 127;
   const int bufn = line_buf_elems<T, MX, 2>(p.nx);
   const int ts = tile_stride(p.nx);
-  cx<T>* tab = reinterpret_cast<cx<T>*>(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
+  cx<T>* tab = lds_table(smem + kTileJ * (bufn > ts ? bufn : ts));  // after lines / tile
   load_twiddles<T, MX, 2>(tab, p.twx);
   T* buf = smem + w * bufn;
   T pre[NT];
@@ -1538,7 +1538,7 @@ __device__ __forceinline__ void yfwd_block_c(const ProbDev& p, int g, int q, dou
 
 template <int MY, int WPL = default_wpl<MY>()>
 __global__ void __launch_bounds__(kBlockY) k_fwd_y_c(ProbDev p) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   const cx<double>* tab = y_tables<double, MY, WPL>(p, smem_raw, true);
   yfwd_block_c<MY, WPL>(p, blockIdx.x, blockIdx.y, smem_raw, tab);
 }
@@ -1620,7 +1620,7 @@ __device__ __forceinline__ void yback_block_c(const ProbDev& p, int g, int q, do
 
 template <int MY, int WPL = default_wpl<MY>()>
 __global__ void __launch_bounds__(kBlockY) k_back_y_c(ProbDev p) {
-  extern __shared__ double smem_raw[];
+  extern __shared__ __align__(16) double smem_raw[];
   const cx<double>* tab = y_tables<double, MY, WPL>(p, smem_raw, true);
   yback_block_c<MY, WPL>(p, blockIdx.x, blockIdx.y, smem_raw, tab);
 }

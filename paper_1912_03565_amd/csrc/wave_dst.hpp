@@ -66,6 +66,15 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 template <typename T>
 __device__ __forceinline__ cx<T> cmi(cx<T> a) { return {a.im, -a.re}; }
 
+// A complex table in LDS at p, which must sit at a multiple of 2 sizeof(T) bytes, with that
+// alignment made known to the compiler: an FP64 entry is then read with one 16-byte access.
+// (Without it the compiler reads the two halves with one paired 8-byte instruction, whose
+// lanes 16 bytes apart cost the LDS four times the cycles of a 16-byte read.)
+template <typename T>
+__device__ __forceinline__ cx<T>* lds_table(T* p) {
+  return reinterpret_cast<cx<T>*>(__builtin_assume_aligned(p, 2 * sizeof(T)));
+}
+
 // index maps of a line buffer: identity, one pad slot per 2^a (a = 3, 4, 5), XOR of the
 // low five bits with bits 4..8 (a bijection inside each aligned block of 32)
 constexpr int kLayId = 0, kLayPad3 = 3, kLayPad4 = 4, kLayPad5 = 5, kLayXor4 = 14;
