@@ -550,9 +550,9 @@ static size_t lds_bytes_x2_t(const cs3d_plan p) {
   return (a > b ? a : b) + tw_bytes<T, MX>();
 }
 
-template <typename T, int MY, int WPL = default_wpl<MY>()>
+template <typename T, int MY, int WPL = default_wpl<MY>(), bool PAIR = false>
 static size_t lds_bytes_y_t(const cs3d_plan p) {
-  return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY, WPL>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
+  return (size_t)YCfg<MY, WPL>::LPB * line_buf_elems<T, MY, WPL, PAIR>(p->d.ny) * sizeof(T) + tw_bytes<T, MY>();
 }
 
 template <typename KernelT, typename... Args>
@@ -655,13 +655,13 @@ static dim3 y_grid(const cs3d_plan p, int nrhs) {
 template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
 static hipError_t run_y_fwd_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   return launch(k_fwd_y<T, MY, WPL, NR, KIND, ROBIN>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
-                lds_bytes_y_t<T, MY, WPL>(p), s, pd, nrhs);
+                lds_bytes_y_t<T, MY, WPL, ypair<T, MY, WPL, true>()>(p), s, pd, nrhs);
 }
 
 template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 static hipError_t run_y_back_n(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStream_t s) {
   return launch(k_back_y<T, MY, WPL, NR, KIND>, y_grid<MY, WPL, NR>(p, nrhs), dim3(kBlockY),
-                lds_bytes_y_t<T, MY, WPL>(p), s, pd, nrhs);
+                lds_bytes_y_t<T, MY, WPL, ypair<T, MY, WPL, false>()>(p), s, pd, nrhs);
 }
 
 static int y_rhs(const cs3d_plan p, int nrhs, int nrmax) {

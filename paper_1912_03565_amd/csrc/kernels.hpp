@@ -102,14 +102,14 @@ struct Tx<0, WPL, KIND> {
 template <typename T, int M, int WPL, int KIND = kDst>
 using TxOut = T[Tx<M, WPL, KIND>::NS];
 
-template <typename T, int M, int WPL, bool BLOCK_SYNC = false, int KIND = kDst>
+template <typename T, int M, int WPL, bool BLOCK_SYNC = false, int KIND = kDst, bool PAIR = false>
 __device__ __forceinline__ void line_dst(T* buf, int N, TxOut<T, M, WPL, KIND>& out, int tl, const cx<T>* tab,
                                          const double* trig, const T* src = nullptr) {
   if constexpr (M == 0) {
     dst_dense<T, KIND>(buf, N, out, tl, trig, src);
     if constexpr (BLOCK_SYNC) __syncthreads();
   } else {
-    dst_fft<T, M, WPL, KIND, BLOCK_SYNC>(buf, out, tl, tab, src);
+    dst_fft<T, M, WPL, KIND, BLOCK_SYNC, PAIR>(buf, out, tl, tab, src);
   }
 }
 
@@ -123,10 +123,10 @@ __device__ __forceinline__ int line_mode(int tl, int s, int N) {
 }
 
 // elements of T in one line buffer (it also holds the line at positions 0..N)
-template <typename T, int M, int WPL>
+template <typename T, int M, int WPL, bool PAIR = false>
 __host__ __device__ constexpr int line_buf_elems(int N) {
   const int line = ((N + 1 + 63) / 64) * 64;
-  return M ? (fft_buf_elems<T, M, WPL>() > line ? fft_buf_elems<T, M, WPL>() : line) : line;
+  return M ? (fft_buf_elems<T, M, WPL, PAIR>() > line ? fft_buf_elems<T, M, WPL, PAIR>() : line) : line;
 }
 
 // twiddle table bytes (FFT path only)
@@ -696,6 +696,7 @@ __global__ void __launch_bounds__(256) k_rhs_sides(ProbDev p) {
 // ---------------------------------------------------------------------------
 constexpr int kNV = 16;  // ceil(1023/64): row values per lane
 constexpr int kXRows = 64 * kTileJ / kTileJ;  // tile rows one pass of an x-pass workgroup covers
+constexpr int kMaxLine = 1023;                // longest x line of the x passes (interior points)
 
 struct XTile {
   int jt, l, r, j;
@@ -763,10 +764,32 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
     }
     __syncthreads();
     settle(pre);  // the next tile's rows, fetched before the transform
-    T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
-    for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
-      const int n0 = idx / kTileJ, jj = idx % kTileJ;
-      G[(long long)n0 * p.ldy + jj] = smem[jj * ts + n0 + 1];
+    // store phase.  FP64: thread (n0, jj) moves modes n0 + 1, n0 + 65, ... of line jj, all
+    // of its LDS reads issued before its stores, so the LDS latency is paid once per tile
+    // rather than once per element (K1 at 1023^3 x 4: 20.6 -> 20.1 ms).  FP32 keeps the
+    // element loop, which measured faster there (39.5 against 43.5 ms for the three
+    // launches of a mixed solve).
+    if constexpr (sizeof(T) == 4) {
+      T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
+      for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
+        const int n0 = idx / kTileJ, jj = idx % kTileJ;
+        G[(long long)n0 * p.ldy + jj] = smem[jj * ts + n0 + 1];
+      }
+    } else {
+      const int tid = opaque((int)threadIdx.x);
+      const int n0 = tid / kTileJ, jj = tid % kTileJ;
+      const T* row = smem + jj * ts + n0 + 1;
+      T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ +
+             (long long)n0 * p.ldy + jj;
+      const long long step = (long long)kXRows * p.ldy;
+      constexpr int NT = (kMaxLine + kXRows - 1) / kXRows;  // rows per thread for the longest line
+      T v[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) v[k] = (n0 + kXRows * k < p.nx) ? row[kXRows * k] : (T)0;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (n0 + kXRows * k < p.nx) G[k * step] = v[k];
+      }
     }
   }
 }
@@ -897,10 +920,25 @@ struct YCfg {
   static constexpr int NRMAX = (NS <= 8 && KIND == kDst) ? 4 : 1;
 };
 
+// Paired exchanges (wave_dst.hpp) in the real y passes, FP64 at M = 1024 with two waves per
+// line; they double the line buffers (16-byte entries).  K2 (FWD) takes them: 21.9 -> 21.5
+// ms at 1023^3 x 4.  K3 does not: no gain there (20.2-20.6 ms either way), and its larger
+// buffers would cap it at two workgroups per CU.
+#ifndef CS3D_PAIR_K2
+#define CS3D_PAIR_K2 1
+#endif
+#ifndef CS3D_PAIR_K3
+#define CS3D_PAIR_K3 0
+#endif
+template <typename T, int MY, int WPL, bool FWD>
+__host__ __device__ constexpr bool ypair() {
+  return pair_exchange_ok<T, MY, WPL>() && (FWD ? CS3D_PAIR_K2 : CS3D_PAIR_K3);
+}
+
 // twiddle tables of a y pass, loaded by the whole block (a barrier follows)
-template <typename T, int MY, int WPL>
+template <typename T, int MY, int WPL, bool PAIR = false>
 __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load) {
-  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL, PAIR>(p.ny);
   cx<T>* tab = lds_table(smem + YCfg<MY, WPL>::LPB * bufn);
   if constexpr (MY != 0) {
     if (load) load_twiddles<T, MY, WPL>(tab, p.twy);
@@ -920,7 +958,7 @@ template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = fal
 __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL, KIND>;
   constexpr int NS = C::NS;
-  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL, ypair<T, MY, WPL, true>()>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
   const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
@@ -989,7 +1027,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       if (r + 1 < nr) fetch(l, r + 1);
       else if (l < p.nz) fetch(l + 1, 0);
       T out[NS] = {};  // lanes past the FFT's own take part with zeros
-      line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
+      line_dst<T, MY, WPL, false, KIND, ypair<T, MY, WPL, true>()>(buf, p.ny, out, tl, tab, p.siny);
       settle(pre);  // the next line, fetched before the transform
       if (r == 0) {
         // lambda^o = beta^o + s_m alpha^o with beta = Z + s_n B, alpha = C + A s_n
@@ -1060,7 +1098,7 @@ template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = fal
 __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
+  const cx<T>* tab = y_tables<T, MY, WPL, ypair<T, MY, WPL, true>()>(p, smem, true);
   const int r0 = blockIdx.y * NR;
   yfwd_block<T, MY, WPL, NR, KIND, ROBIN>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }
@@ -1073,7 +1111,7 @@ template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
   using C = YCfg<MY, WPL, KIND>;
   constexpr int NS = C::NS;
-  const int bufn = line_buf_elems<T, MY, WPL>(p.ny);
+  const int bufn = line_buf_elems<T, MY, WPL, ypair<T, MY, WPL, false>()>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
   const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
@@ -1143,7 +1181,7 @@ __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int
       }
       if (r == 0 && l > 1) fetch_c(l - 1, pcn);
       T out[NS];
-      line_dst<T, MY, WPL, false, KIND>(buf, p.ny, out, tl, tab, p.siny);
+      line_dst<T, MY, WPL, false, KIND, ypair<T, MY, WPL, false>()>(buf, p.ny, out, tl, tab, p.siny);
       settle(pd);  // d' and c' of the next step, fetched before the transform
       settle(pcn);
 #pragma unroll
@@ -1160,7 +1198,7 @@ template <typename T, int MY, int WPL, int NR, int KIND = kDst>
 __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  const cx<T>* tab = y_tables<T, MY, WPL>(p, smem, true);
+  const cx<T>* tab = y_tables<T, MY, WPL, ypair<T, MY, WPL, false>()>(p, smem, true);
   const int r0 = blockIdx.y * NR;
   yback_block<T, MY, WPL, NR, KIND>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
 }

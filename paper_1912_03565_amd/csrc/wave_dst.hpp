@@ -229,6 +229,29 @@ __host__ __device__ constexpr int exch_lay() {
   else return K == 0 ? kLayPad5 : (K == 1 ? kLayPad3 : kLayId);
 }
 
+// Paired exchanges (FP64, M = 1024, two waves per line): the real and imaginary parts of a
+// value move through the buffer together as one 16-byte entry, so an exchange takes one
+// write, one read and two barriers per value instead of two, two and four.  The entry maps
+// of exchanges 0, 1, 2 (one pad entry per 16; an XOR of the low four bits with bits 3..6;
+// identity) make every quarter-wave's 16-byte accesses fall on distinct 16-byte bank groups.
+template <typename T, int M, int WPL>
+__host__ __device__ constexpr bool pair_exchange_ok() {
+  return sizeof(T) == 8 && M == 1024 && WPL == 2;
+}
+
+template <int K>
+__host__ __device__ constexpr int pair_lay(int p) {
+  if constexpr (K == 0) {
+    return p + (p >> 4);
+  } else if constexpr (K == 1) {
+    return p ^ ((p >> 3) & 15);
+  } else {
+    return p;
+  }
+}
+
+constexpr int kPairEntries = 1024 + 1024 / 16;  // entries the maps above need at M = 1024
+
 template <int M, int WPL>
 __host__ __device__ constexpr int fft_slots() {
   constexpr int a = lay_slots<exch_lay<M, WPL, 0>()>(M), b = lay_slots<exch_lay<M, WPL, 1>()>(M),
@@ -238,8 +261,10 @@ __host__ __device__ constexpr int fft_slots() {
 }
 
 // LDS elements of T in one line buffer
-template <typename T, int M, int WPL>
+template <typename T, int M, int WPL, bool PAIR = false>
 __host__ __device__ constexpr int fft_buf_elems() {
+  static_assert(!PAIR || pair_exchange_ok<T, M, WPL>(), "paired exchanges: FP64, M = 1024, two waves");
+  if constexpr (PAIR) return 2 * kPairEntries;
   return sizeof(T) == 8 ? fft_slots<M, WPL>() : 2 * fft_slots<M, WPL>();
 }
 
@@ -313,11 +338,20 @@ __device__ __forceinline__ int fft_ipos(int tl, int s) {
 }
 
 // exchange K of the plan: after stage (RS, NSP), before a stage of radix RS2
-template <typename T, int M, int WPL, int RS, int NSP, int RS2, int K>
+template <typename T, int M, int WPL, int RS, int NSP, int RS2, int K, bool PAIR = false>
 __device__ __forceinline__ void fft_exchange(LineRegs<T, M, WPL>& v, T* buf, int tl) {
   constexpr int R = FftGeom<M, WPL>::R;
   constexpr int LAY = exch_lay<M, WPL, K>();
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (PAIR) {
+    static_assert(pair_exchange_ok<T, M, WPL>(), "paired exchanges: FP64, M = 1024, two waves");
+    cx<T>* cb = lds_table(buf);
+#pragma unroll
+    for (int s = 0; s < R; ++s) cb[pair_lay<K>(fft_opos<M, WPL, RS, NSP, kLayId>(tl, s))] = v[s];
+    line_sync<WPL>();
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[s] = cb[pair_lay<K>(fft_ipos<M, WPL, RS2, kLayId>(tl, s))];
+    line_sync<WPL>();
+  } else if constexpr (sizeof(T) == 4) {
     cx<T>* cb = reinterpret_cast<cx<T>*>(buf);
 #pragma unroll
     for (int s = 0; s < R; ++s) cb[fft_opos<M, WPL, RS, NSP, LAY>(tl, s)] = v[s];
@@ -376,7 +410,7 @@ __device__ __forceinline__ void fill_stage_tables(cx<T>* st, const double2* __re
   }
 }
 
-template <typename T, int M, int WPL>
+template <typename T, int M, int WPL, bool PAIR = false>
 __device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, const cx<T>* st) {
   constexpr int R = FftGeom<M, WPL>::R;
   if constexpr (R == 4 && M == 64) {
@@ -419,11 +453,11 @@ __device__ __forceinline__ void fft_run(LineRegs<T, M, WPL>& v, T* buf, int tl, 
     fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
   } else if constexpr (R == 8 && M == 1024) {
     fft_stage<T, M, WPL, 8, 1, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 1, 8, 0>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 1, 8, 0, PAIR>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 8, 0>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 8, 8, 1>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 8, 8, 1, PAIR>(v, buf, tl);
     fft_stage<T, M, WPL, 8, 64, 56>(v, tl, st);
-    fft_exchange<T, M, WPL, 8, 64, 2, 2>(v, buf, tl);
+    fft_exchange<T, M, WPL, 8, 64, 2, 2, PAIR>(v, buf, tl);
     fft_stage<T, M, WPL, 2, 512, 504>(v, tl, st);
   } else {
     static_assert(R == 16 && M == 1024, "no stage plan");
@@ -451,7 +485,7 @@ __host__ __device__ constexpr int fft_out_slots() {
   return FftGeom<M, WPL>::R + (KIND == kDct ? 1 : 0);
 }
 
-template <typename T, int M, int WPL, int KIND, bool BLOCK_SYNC = false>
+template <typename T, int M, int WPL, int KIND, bool BLOCK_SYNC = false, bool PAIR = false>
 __device__ __forceinline__ void dst_fft(T* buf, T (&out)[fft_out_slots<M, WPL, KIND>()], int tl,
                                         const cx<T>* tab, const T* src = nullptr) {
   constexpr int R = FftGeom<M, WPL>::R, L = FftGeom<M, WPL>::L;
@@ -486,7 +520,7 @@ __device__ __forceinline__ void dst_fft(T* buf, T (&out)[fft_out_slots<M, WPL, K
     line_sync<WPL>();
   }
   if (tl < L) {
-    fft_run<T, M, WPL>(v, buf, tl, tab + M);
+    fft_run<T, M, WPL, PAIR>(v, buf, tl, tab + M);
 #pragma unroll
     for (int s = 0; s < R / 2; ++s) {
       if constexpr (KIND == kDst) {
