@@ -11,8 +11,12 @@ measures it two ways:
   * on a discrete manufactured solution of the same operator: random U* in [-1, 1],
     F = A U* formed in extended precision (eq. stencil27) and rounded to FP64, solved by
     the FP64 oracle (relative L2 and max errors against U*).
+With --full it also stores the extended-precision solution of the workload at sampled
+points (every corner, edge midpoint and face centre, plus seeded random points), rounded to
+FP64, with its 2-norm and largest magnitude, so that a GPU result can be compared with the
+extended-precision oracle point by point at full size.
 Calls only the oracle (``oracle/``) and the problem definitions (``workloads/``).  About 1.5
-minutes and 25 GB; with --full about 25 minutes more.
+minutes and 25 GB; with --full about 35 minutes more.
 """
 import json
 import os
@@ -39,15 +43,33 @@ def manufactured_error(p, seed):
             "min_abs_pivot": float(r.minpiv), "seed": seed}
 
 
-def workload_error(p):
-    """The FP64 oracle against the extended-precision oracle on the workload's own system."""
+def sample_indices(nz, ny, nx, count, seed):
+    """0-based (z, y, x) indices of the interior array: corners, edge midpoints, face centres
+    and `count` seeded random points."""
+    pts = set()
+    for z in (0, nz // 2, nz - 1):
+        for y in (0, ny // 2, ny - 1):
+            for x in (0, nx // 2, nx - 1):
+                pts.add((z, y, x))
+    rng = np.random.default_rng(seed)
+    while len(pts) < 27 + count:
+        pts.add((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
+    return sorted(pts)
+
+
+def workload_error(p, samples=4000):
+    """The FP64 oracle against the extended-precision oracle on the workload's own system,
+    and the extended-precision solution at sampled points."""
     kw = dict(scheme=p.scheme, f=p.f[0].numpy(), hx=p.hx, hy=p.hy, hz=p.hz, k2=p.k2, k2_z=p.k2_z,
               k2_zz=p.k2_zz, gamma=p.gamma)
     u64 = O.solve(**kw).U
     ref = O.solve(**kw, dtype=np.longdouble).U
     d = u64 - ref
+    pts = sample_indices(p.nz, p.ny, p.nx, samples, seed=p.nx)
     return {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
-            "rel_max": float(np.max(np.abs(d)) / np.max(np.abs(ref)))}
+            "rel_max": float(np.max(np.abs(d)) / np.max(np.abs(ref))),
+            "ext_norm2": float(np.linalg.norm(ref)), "ext_absmax": float(np.max(np.abs(ref))),
+            "points": pts, "ext_values": [float(ref[z, y, x]) for (z, y, x) in pts]}
 
 
 def main():
