@@ -87,10 +87,15 @@ def measured_traffic(kernel, nrhs):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(n, planes):
-    """Time the oracle (FP64, as it stands) on a slab of `planes` z-planes of one right-hand
-    side of the same workload: RHS operator, forward 2-D DST, the Thomas sweep over the
-    matching share of modal columns (all N_z planes), inverse 2-D DST."""
+def cpu_baseline(n, planes, checks=None):
+    """The CPU leg: time the oracle (FP64, as it stands) on a slab of `planes` z-planes of
+    one right-hand side of the same workload (RHS operator, forward 2-D DST, the Thomas
+    sweep over the matching share of modal columns (all N_z planes), inverse 2-D DST).
+
+    With `checks` it also checks GPU results of this run against the oracle (host data
+    copied out of the GPU legs): the 255^3 solve against a full FP64 oracle solve
+    (relative L2 and max errors), and the oracle's residual of eq. stencil27 at sampled
+    points of the timed 1023^3 FP64 solution."""
     import numpy as np
     import torch
 
@@ -114,15 +119,163 @@ def cpu_baseline(n, planes):
     Fb = O.dst2(F)
     lam = O.modal_eigenvalues(W, n, P)            # P x N modal columns over all N_z rows
     rng = np.random.default_rng(0)
-    Fcols = rng.standard_normal((n, P, n))
+    Fcols = rng.standard_normal((n, P, n))        # synthetic Thomas input (the sweep's cost only)
     Wm, _, _ = O.thomas(lam, Fcols)
     U = O.dst2(Fb)
     t = time.perf_counter() - t0
     del U, Wm, lam, Fcols
-    return {"value": P * n * n / t, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{P} of {n} z-planes of one right-hand side: RHS operator, forward and inverse "
-                      f"2-D DST by dense sine sums, Thomas sweep over {P}x{n} of the {n}x{n} modal "
-                      f"columns; {t:.1f} s on {threads} host threads"}
+    out = {"value": P * n * n / t, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{P} of {n} z-planes of one right-hand side: RHS operator, forward and inverse "
+                     f"2-D DST by dense sine sums, Thomas sweep over {P}x{n} of the {n}x{n} modal "
+                     f"columns (the sweep's input is synthetic: it times the recurrence only); "
+                     f"{t:.1f} s on {threads} host threads"}
+    if not checks:
+        return out
+    oc = {}
+    if "config2" in checks:
+        c = checks["config2"]
+        q = WL.config2(n=c["n"], device="cpu")
+        t0 = time.perf_counter()
+        ref = O.solve(q.scheme, q.f[0].numpy(), q.hx, q.hy, q.hz, q.k2, q.k2_z, q.k2_zz, q.gamma, None, None)
+        d = c["u"] - ref.U
+        oc["config2_fp64_vs_fp64_oracle"] = {
+            "rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref.U)),
+            "rel_max": float(np.abs(d).max() / np.abs(ref.U).max()),
+            "oracle_s": round(time.perf_counter() - t0, 2)}
+        # the FP64 oracle's own distance from the extended-precision oracle on this workload
+        # (stored by tests/golden/make_fp64_floor.py --full from the oracle alone)
+        try:
+            with open(os.path.join(ROOT, "tests", "golden", "fp64_floor.json")) as fh:
+                w = json.load(fh)["config2_255"]["workload"]
+            oc["config2_fp64_vs_fp64_oracle"]["fp64_oracle_vs_extended"] = {
+                "rel_l2": w["rel_l2"], "rel_max": w["rel_max"]}
+        except (OSError, KeyError, ValueError):
+            pass
+    if "points" in checks:
+        c = checks["points"]
+        res = []
+        for (l, j, i), (az, ay, ax), fb, U3 in zip(c["points"], c["starts"], c["fblocks"], c["ublocks"]):
+            Fb7 = O.rhs("helm6", fb, h, h, h, k2[az:az + 7], k2z[az:az + 7])
+            Fp = Fb7[l - 1 - az, j - 1 - ay, i - 1 - ax]
+            Wl = W[l - 1:l]
+            AU = O.apply_operator(Wl, U3)[0, 0, 0]
+            scale = abs(Fp) + float(O.apply_operator(np.abs(Wl), np.abs(U3))[0, 0, 0])
+            res.append(abs(Fp - AU) / scale)
+        oc["fp64_1023_point_residual"] = {
+            "points": len(res), "max": float(max(res)),
+            "what": "|F - A U| / (|F| + sum |w||U|) of the oracle's RHS and 27-point operators at "
+                    "sampled interior, face, edge and corner points of right-hand side 0"}
+    out["oracle_checks"] = oc
+    return out
+
+
+def sample_blocks(p, u, r, count=48, seed=11):
+    """Neighbourhoods of sampled points of right-hand side r (closed-grid f blocks of 7^3
+    around each point, U on its 3^3 neighbourhood with zero outside the interior), copied
+    to the host for the oracle's point residuals."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    n = p.nx
+    pts = {tuple(int(v) for v in rng.integers(1, n + 1, size=3)) for _ in range(count)}
+    for l in (1, 2, n - 1, n):
+        for j in (1, n):
+            for i in (1, n // 2, n):
+                pts.add((l, j, i))
+    pts = sorted(pts)
+    start = lambda idx: min(max(idx - 3, 0), n - 5)  # noqa: E731 - block faces = box faces near them
+    starts, fbl, ubl = [], [], []
+    for (l, j, i) in pts:
+        az, ay, ax = start(l), start(j), start(i)
+        starts.append((az, ay, ax))
+        fbl.append(p.f[r, az:az + 7, ay:ay + 7, ax:ax + 7].cpu().numpy())
+        U3 = np.zeros((3, 3, 3))
+        z0, y0, x0 = max(l - 1, 1), max(j - 1, 1), max(i - 1, 1)
+        z1, y1, x1 = min(l + 1, n), min(j + 1, n), min(i + 1, n)
+        U3[z0 - l + 1:z1 - l + 2, y0 - j + 1:y1 - j + 2, x0 - i + 1:x1 - i + 2] = \
+            u[r, z0 - 1:z1, y0 - 1:y1, x0 - 1:x1].cpu().numpy()
+        ubl.append(U3)
+    return {"points": pts, "starts": starts, "fblocks": fbl, "ublocks": ubl}
+
+
+def copy_bandwidth(dev, gib=2, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `gib` GiB."""
+    import torch
+
+    src = torch.ones(gib * 2 ** 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 8 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def small_configs(cs3d, dev, steps, warmup):
+    """The smaller workloads: 63^3 (HELM4, k = 10, one right-hand side: launch latency),
+    255^3 (HELM6, k = 20(1 + 0.5 sin 2 pi z), smooth + noise RHS) and 511^3 (HELM6,
+    k = 50(1 + 0.3 z), Gaussian RHS; FP64 and mixed).  Returns the results and the 255^3
+    solution on the host for the oracle check of the CPU leg."""
+    import torch
+
+    import workloads as WL
+
+    out, keep = {}, {}
+
+    def timed(p, precision, reps, f=None):
+        plan = cs3d.plan_for_problem(p, precision=precision, refine_steps=2, max_rhs=1, device=dev)
+        f = p.f.to(dev) if f is None else f
+        u = torch.empty(plan.interior_shape(1), dtype=torch.float64, device=dev)
+        for _ in range(max(warmup, 1)):
+            plan.solve(f, out=u)
+        plan.reset_timers()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            plan.solve(f, out=u)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st = plan.stats()
+        plan.close()
+        return u, ms, st
+
+    p1 = WL.config1()
+    _, ms, st = timed(p1, "fp64", 100)
+    out["config1_helm4_63^3"] = {"us_per_solve": round(ms * 1e3, 2), "value": round(63 ** 3 / (ms / 1e3), 1),
+                                 "unit": "unknowns/s", "note": "one right-hand side, eager launches"}
+    log(f"[bench] 63^3 helm4: {ms * 1e3:.1f} us per solve")
+    p2 = WL.config2(n=255, device=dev)
+    u2, ms, st = timed(p2, "fp64", max(steps, 5))
+    keep["config2"] = {"n": 255, "u": u2[0].cpu().numpy()}
+    out["config2_helm6_255^3"] = {"ms_per_solve": round(ms, 4), "value": round(255 ** 3 / (ms / 1e3), 1),
+                                  "unit": "unknowns/s", "stage_ms": [round(x, 4) for x in st["stage_ms"]],
+                                  "min_abs_pivot": st["min_abs_pivot"]}
+    log(f"[bench] 255^3 helm6: {ms:.3f} ms per solve")
+    del p2, u2
+    p3 = WL.config3(n=511, device=dev)
+    u64, ms64, st64 = timed(p3, "fp64", max(steps, 5), f=p3.f)
+    umx, msmx, stmx = timed(p3, "mixed", max(steps, 5), f=p3.f)
+    d = float(torch.linalg.vector_norm(umx[0] - u64[0]) / torch.linalg.vector_norm(u64[0]))
+    out["config3_helm6_511^3"] = {
+        "fp64_ms": round(ms64, 4), "mixed_ms": round(msmx, 4), "speedup_mixed_vs_fp64": round(ms64 / msmx, 4),
+        "fp64_value": round(511 ** 3 / (ms64 / 1e3), 1), "mixed_value": round(511 ** 3 / (msmx / 1e3), 1),
+        "unit": "unknowns/s", "mixed_rel_diff_vs_fp64": d,
+        "mixed_residual_history": stmx["residual_history"][: stmx["refine_done"] + 1]}
+    log(f"[bench] 511^3 helm6: fp64 {ms64:.3f} ms, mixed {msmx:.3f} ms, diff {d:.2e}")
+    del p3, u64, umx
+    torch.cuda.empty_cache()
+    return out, keep
 
 
 def time_path(cs3d, p, nrhs, precision, steps, warmup, dev, autotune=True):
@@ -296,12 +449,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1023)
     ap.add_argument("--nrhs", type=int, default=4)
-    ap.add_argument("--cpu-planes", type=int, default=96)
+    ap.add_argument("--cpu-planes", type=int, default=192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="time the FP64 path only")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
     ap.add_argument("--no-complex", action="store_true", help="skip the absorbing-medium (complex k) timing")
     ap.add_argument("--no-neumann", action="store_true", help="skip the Neumann-sides timing")
+    ap.add_argument("--no-small", action="store_true", help="skip the 63^3, 255^3 and 511^3 workloads")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune each plan before timing (the defaults are the tuned shapes of this workload)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -326,6 +480,9 @@ def main():
 
     tune = args.autotune
     u64, ms64, st64 = time_path(cs3d, p, nrhs, "fp64", args.steps, args.warmup, dev, tune)
+    checks = {}
+    if not args.no_cpu_baseline and n == 1023:
+        checks["points"] = sample_blocks(p, u64, 0)
     paths = {"fp64": {"ms_per_step": round(ms64, 4), "value": round(unknowns / (ms64 / 1e3), 1),
                       "stage_ms": [round(x, 4) for x in st64["stage_ms"]],
                       "min_abs_pivot": st64["min_abs_pivot"], "tuning": st64["tuning"]}}
@@ -366,6 +523,24 @@ def main():
                "algorithmic_GBs": round(sb[i] / (stage_ms[i] / 1e3) / 1e9, 1) if stage_ms[i] > 0 else None}
               for i in range(len(sb))]
     whole_gbs = sum(sb) / (ms64 / 1e3) / 1e9
+    copy_gbs = copy_bandwidth(dev)
+    log(f"[bench] plain 2 GiB device copy: {copy_gbs:.1f} GB/s")
+    roofline["measured_copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    floor_gbs = 48 * unknowns / (ms64 / 1e3) / 1e9
+    whole_path = {"fp64_ms_per_step": round(ms64, 4),
+                  "design_bytes_per_unknown": round(sum(stage_bytes(n, n, n, nrhs, 8)) / unknowns, 2),
+                  "design_GBs": round(whole_gbs, 1),
+                  "floor_bytes_per_unknown": 48,
+                  "floor_GBs": round(floor_gbs, 1),
+                  "floor_frac_of_peak": round(floor_gbs / HBM_PEAK_GBS, 4),
+                  "floor_frac_of_copy": round(floor_gbs / copy_gbs, 4),
+                  "design_frac_of_peak": round(whole_gbs / HBM_PEAK_GBS, 4),
+                  "design_frac_of_copy": round(whole_gbs / copy_gbs, 4)}
+    for row in stages:
+        if row["algorithmic_GBs"]:
+            row["frac_of_peak"] = round(row["algorithmic_GBs"] / HBM_PEAK_GBS, 4)
+            row["frac_of_copy"] = round(row["algorithmic_GBs"] / copy_gbs, 4)
 
     if args.traffic_probe:
         src = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
@@ -381,6 +556,11 @@ def main():
         batch = batch_bench(cs3d, dev, args.steps, args.warmup)
     del p  # the main workload's fields
     torch.cuda.empty_cache()
+    small = None
+    if not args.no_small:
+        small, keep = small_configs(cs3d, dev, args.steps, args.warmup)
+        if not args.no_cpu_baseline:
+            checks.update(keep)
     cplx = None
     if not args.no_complex:
         cplx = complex_bench(cs3d, dev, n, max(1, nrhs // 2), args.steps, args.warmup)
@@ -391,7 +571,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_planes} planes")
-        cpu = cpu_baseline(n, args.cpu_planes)
+        cpu = cpu_baseline(n, args.cpu_planes, checks)
         cpu["value"] = round(cpu["value"], 1)
         log(f"[bench] cpu baseline {cpu['value']:.3e} unknowns/s")
 
@@ -409,6 +589,8 @@ def main():
         "stages": stages,
         "paths": paths,
         "fp64_path_algorithmic_GBs": round(whole_gbs, 1),
+        "whole_path": whole_path,
+        "small_configs": small,
         "batch": batch,
         "complex_k": cplx,
         "neumann_sides": neu,

@@ -72,7 +72,7 @@ __host__ __device__ inline int x_items(int ldy, int nz) { return (ldy / kTileJ) 
 __host__ __device__ inline int y_items(int nx, int lpb) { return (nx + lpb - 1) / lpb; }
 // RHS items: 64 x 16 tiles times z-chunks
 __host__ __device__ inline int rhs_items(int nx, int ny, int nz, int zchunk) {
-  return ((nx + kRX - 1) / kRX) * ((ny + kRY - 1) / kRY) * ((nz + zchunk - 1) / zchunk);
+  return ((nx + kRX - 1) / kRX) * ((ny + kRYBatch - 1) / kRYBatch) * ((nz + zchunk - 1) / zchunk);
 }
 
 // Call fn(std::integral_constant<int, M>) for the member's transform size: FFT lengths up
@@ -99,15 +99,15 @@ __device__ __forceinline__ void dispatch_m(int M, Fn&& fn) {
 // ---------------------------------------------------------------------------
 // RHS pass
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kRThreads) kb_rhs(BatchArgs b) {
-  __shared__ double win[kRSlots][kSY * kSX];
+__global__ void __launch_bounds__(kRThreadsBatch) kb_rhs(BatchArgs b) {
+  __shared__ double win[kRSlots][RTile<kRYBatch>::SY * kSX];
   __shared__ double kt[2 * kZMax];
   for (int item = xcd_order(blockIdx.x, gridDim.x); item < b.total; item += gridDim.x) {
     const int k = find_slot(b, item);
     const ProbDev p = vload_desc(b.P + vload_int(b.perm + k));
     const int t = item - vload_int(b.start + k);
-    const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRY - 1) / kRY;
-    rhs_block<true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win, kt);
+    const int nbx = (p.nx + kRX - 1) / kRX, nby = (p.ny + kRYBatch - 1) / kRYBatch;
+    rhs_block<kRYBatch, true>(p, t % nbx, (t / nbx) % nby, t / (nbx * nby), 0, win, kt);
   }
 }
 

@@ -774,9 +774,9 @@ static hipError_t run_rhs(const cs3d_plan p, const ProbDev& pd, int nrhs, hipStr
     return hipGetLastError();
   }
   const int nzc = (pd.nz + pd.zchunk - 1) / pd.zchunk;
-  dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRY - 1) / kRY, nzc * nrhs);
+  dim3 grid((p->d.nx + kRX - 1) / kRX, (p->d.ny + kRYPlan - 1) / kRYPlan, nzc * nrhs);
   if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreads), 0, s, pd);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kRThreadsPlan), 0, s, pd);
   hipError_t e = hipGetLastError();
   // face corrections: x and y faces (6th order), z faces (6th order and the lift)
   const bool h6 = p->d.scheme == CS3D_HELM6;
@@ -1330,15 +1330,18 @@ static double line_cost(int f, int N) { return f ? f * std::log2((double)f) : 0.
 
 static int y_wpl(int fy) { return fy == 1024 ? 2 : 1; }
 
-// LDS elements (doubles) of one line buffer, as line_buf_elems for T = double with the
-// default waves per line
+// LDS elements (doubles) of one line buffer of the y passes, as line_buf_elems for T = double
+// with the default waves per line; at 1024 points the larger of the forward pass's buffer
+// (paired exchanges) and the backward pass's, since both passes share the size
 static size_t line_elems(int f, int N) {
+  constexpr int W = default_wpl<1024>();
   switch (f) {
     case 64: return line_buf_elems<double, 64, 1>(N);
     case 128: return line_buf_elems<double, 128, 1>(N);
     case 256: return line_buf_elems<double, 256, 1>(N);
     case 512: return line_buf_elems<double, 512, default_wpl<512>()>(N);
-    case 1024: return line_buf_elems<double, 1024, default_wpl<1024>()>(N);
+    case 1024: return std::max(line_buf_elems<double, 1024, W, ypair<double, 1024, W, true>()>(N),
+                               line_buf_elems<double, 1024, W, ypair<double, 1024, W, false>()>(N));
     default: return line_buf_elems<double, 0, 1>(N);
   }
 }
@@ -1370,7 +1373,7 @@ static cs3d_status batch_grids_t(cs3d_batch b) {
                                reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, true>),
                                reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, false>),
                                reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, false>)};
-  const int threads[kPasses] = {kRThreads, 64 * kTileJ, kBlockY, kBlockY, 64 * kTileJ};
+  const int threads[kPasses] = {kRThreadsBatch, 64 * kTileJ, kBlockY, kBlockY, 64 * kTileJ};
   for (int k = 0; k < kPasses; ++k) {
     if (b->lds[k] > 160 * 1024) return CS3D_E_UNSUPPORTED;
     if (b->lds[k] > 64 * 1024 &&
@@ -1437,7 +1440,7 @@ static hipError_t batch_pass_t(const cs3d_batch b, int pass, hipStream_t s) {
   const BatchArgs a{b->dP, lst, lst + b->n + 1, b->n, b->total[pass]};
   const dim3 g(b->grid[pass]);
   switch (pass) {
-    case kPassRhs: hipLaunchKernelGGL(kb_rhs, g, dim3(kRThreads), 0, s, a); break;
+    case kPassRhs: hipLaunchKernelGGL(kb_rhs, g, dim3(kRThreadsBatch), 0, s, a); break;
     case kPassXf: hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, true>), g, dim3(64 * kTileJ), b->lds[pass], s, a); break;
     case kPassYf: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, true>), g, dim3(kBlockY), b->lds[pass], s, a); break;
     case kPassYb: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, false>), g, dim3(kBlockY), b->lds[pass], s, a); break;

@@ -182,15 +182,15 @@ __device__ __forceinline__ int linear_block() {
 }
 
 // ---------------------------------------------------------------------------
-// K0: RHS operator + lift.  Tile 64 (x) x 16 (y) interior points, 256 threads; thread
+// K0: RHS operator + lift.  Tile 64 (x) x RY (y) interior points, 16 RY threads; thread
 // (lane, wave) owns column x0 + lane, rows y0 + 4 wave .. + 3.  The workgroup marches
 // over a z-chunk with a four-plane ring of halo tiles in LDS (the planes l-1, l, l+1
 // and the next one) and two further planes in flight in registers; every thread keeps
 // its own column of the five planes l-2 .. l+2 in registers, so the z-differences and
 // the y-differences inside its rows cost no LDS reads.
 // ---------------------------------------------------------------------------
-constexpr int kRX = 64, kRY = 16, kRH = 2, kZChunk = 32;  // kZChunk: default planes per workgroup
-constexpr int kSX = kRX + 2 * kRH, kSY = kRY + 2 * kRH;
+constexpr int kRX = 64, kRH = 2, kZChunk = 32;  // kZChunk: default planes per workgroup
+constexpr int kSX = kRX + 2 * kRH;
 constexpr int kRSlots = 4;  // LDS planes
 
 __device__ __forceinline__ double d4_onesided(const double* c, long long s, bool low) {
@@ -241,16 +241,27 @@ __device__ __forceinline__ double face_corr(const ProbDev& p, int r, int i, int 
   return F;
 }
 
-constexpr int kRThreads = 256;
+// RHS tiles of 64 x RY points, four rows per thread: 16 RY threads.  The plan's pass takes
+// 64 x 64 tiles (one workgroup of 16 waves per CU, 156 KB of LDS): their halo re-reads
+// 1.09x the closed grid where 64 x 16 tiles re-read 1.30x (measured at 1023^3 x 4, FETCH_SIZE;
+// 17.0 against 17.3 ms).  The batch keeps 64 x 16 tiles (its members are small, and the
+// larger tile spills in the batch kernel).
+template <int RY>
+struct RTile {
+  static constexpr int Y = RY, ROWS = 4, THREADS = 64 * RY / ROWS, SY = RY + 2 * kRH;
+  static constexpr int LOADS = (SY * kSX + THREADS - 1) / THREADS;  // plane-tile elements per thread
+};
+constexpr int kRYPlan = 64, kRYBatch = 16;
+constexpr int kRThreadsPlan = RTile<kRYPlan>::THREADS, kRThreadsBatch = RTile<kRYBatch>::THREADS;
 constexpr int kZMax = 512;  // largest z-chunk of the z-marching passes (the tuning range)
-constexpr int kRRows = kRY / (kRThreads / 64);                    // y-rows per thread (4)
-constexpr int kRLoads = (kSY * kSX + kRThreads - 1) / kRThreads;  // plane-tile elements per thread
 
 // one 64 x 16 tile (bx, by) over the z-chunk zc of right-hand side r.  FACES: add the
 // corrections of the points on the faces of the box here (else k_rhs_faces does it)
-template <bool FACES>
+template <int RY, bool FACES>
 __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int zc, int r,
-                                          double (*win)[kSY * kSX], double* kt) {
+                                          double (*win)[RTile<RY>::SY * kSX], double* kt) {
+  constexpr int kRY = RY, kSY = RTile<RY>::SY, kRThreads = RTile<RY>::THREADS;
+  constexpr int kRRows = RTile<RY>::ROWS, kRLoads = RTile<RY>::LOADS;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = 1 + bx * kRX, y0 = 1 + by * kRY;
   const int lb = 1 + zc * p.zchunk;
@@ -441,13 +452,13 @@ __device__ __forceinline__ void rhs_block(const ProbDev& p, int bx, int by, int 
 
 // grid: (x tiles) x (y tiles) x (z chunks x right-hand sides), taken in XCD order; the
 // face corrections follow in k_rhs_faces
-__global__ void __launch_bounds__(kRThreads) k_rhs(ProbDev p) {
-  __shared__ double win[kRSlots][kSY * kSX];
+__global__ void __launch_bounds__(kRThreadsPlan) k_rhs(ProbDev p) {
+  __shared__ double win[kRSlots][RTile<kRYPlan>::SY * kSX];
   __shared__ double kt[2 * kZMax];
   const int nzc = (p.nz + p.zchunk - 1) / p.zchunk;
   const int T = xcd_order(linear_block(), gridDim.x * gridDim.y * gridDim.z);
   const int bx = T % gridDim.x, by = (T / gridDim.x) % gridDim.y, bz = T / (gridDim.x * gridDim.y);
-  rhs_block<false>(p, bx, by, bz % nzc, bz / nzc, win, kt);
+  rhs_block<kRYPlan, false>(p, bx, by, bz % nzc, bz / nzc, win, kt);
 }
 
 // Corrections of F on one pair of faces of the interior box (axis 0: x, 1: y, 2: z), one
