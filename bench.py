@@ -397,6 +397,44 @@ def complex_bench(cs3d, dev, n, nrhs, steps, warmup):
     return out
 
 
+def robin_bench(cs3d, dev, n, nrhs, steps, warmup):
+    """The 6th-order workload with Robin z faces (alpha u_z + beta u = g on z = 0 and z = 1,
+    alpha = (1, 2), beta = (0.7, -1.5)): k = 80 exp(-z), an n x n x (n - 2) interior grid whose
+    two z-face planes are unknowns too (n^3 unknowns per right-hand side), f and face data
+    U[-1, 1] (seeds 107000...)."""
+    import torch
+
+    import workloads as WL
+
+    p = WL.robin_noise_problem(n, n, n - 2, "helm6", seed=107000, device=dev, nrhs=nrhs,
+                               prof=WL.problems.K_CONFIG5)
+    plan = cs3d.plan_for_problem(p, max_rhs=nrhs, device=dev)
+    u = torch.empty(plan.interior_shape(nrhs), dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        plan.solve(p.f, p.g_lo, p.g_hi, out=u)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.solve(p.f, p.g_lo, p.g_hi, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = plan.stats()
+    unknowns = nrhs * n ** 3
+    out = {"workload": f"helm6_kexp_robin_z_{n}x{n}x{n - 2}_x{nrhs}rhs", "unknowns": unknowns,
+           "ms_per_step": round(ms, 4), "value": round(unknowns / (ms / 1e3), 1), "unit": "unknowns/s",
+           "stage_ms": [round(x, 4) for x in st["stage_ms"]], "min_abs_pivot": st["min_abs_pivot"],
+           "bad_pivots": st["bad_pivots"]}
+    log(f"[bench] robin z faces: {ms:.3f} ms per step of {nrhs} x {n ** 3} unknowns; stages {out['stage_ms']}")
+    plan.close()
+    del plan, u, p
+    torch.cuda.empty_cache()
+    return out
+
+
 def neumann_bench(cs3d, dev, n, nrhs, steps, warmup):
     """The 6th-order workload with Neumann sides (du/dn = 0 on the x and y faces, DCT-I
     transforms): k = 80 exp(-z), n^3 interior grid whose (n+2)^2 n nodes are all unknown,
@@ -455,6 +493,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch timing")
     ap.add_argument("--no-complex", action="store_true", help="skip the absorbing-medium (complex k) timing")
     ap.add_argument("--no-neumann", action="store_true", help="skip the Neumann-sides timing")
+    ap.add_argument("--no-robin", action="store_true", help="skip the Robin-z-faces timing")
     ap.add_argument("--no-small", action="store_true", help="skip the 63^3, 255^3 and 511^3 workloads")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune each plan before timing (the defaults are the tuned shapes of this workload)")
@@ -567,6 +606,9 @@ def main():
     neu = None
     if not args.no_neumann:
         neu = neumann_bench(cs3d, dev, min(n, 511), nrhs, args.steps, args.warmup)
+    rob = None
+    if not args.no_robin:
+        rob = robin_bench(cs3d, dev, n, nrhs, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -594,6 +636,7 @@ def main():
         "batch": batch,
         "complex_k": cplx,
         "neumann_sides": neu,
+        "robin_z_faces": rob,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1047,7 +1047,25 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
         const double b0 = Ll[4] + ctn * Ll[5], a0 = Ll[6] + Ll[7] * ctn;
         const double bp = Ll[8] + ctn * Ll[9], ap = Ll[10] + Ll[11] * ctn;
         double* Cl = p.C + (long long)(l - 1) * lstride + nbase;
-        if constexpr (kHoistS) {
+        if constexpr (kHoistS && NR == 1) {
+          // one right-hand side: each mode's pivot is applied to d' at once, so no array of
+          // eigenvalues and reciprocals stays live across the modes
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
+            const bool valid = active && m > 0;
+            const double sm = smv[s];
+            double lm = am * sm + bm, l0 = a0 * sm + b0, lpv = ap * sm + bp;
+            if constexpr (ROBIN) robin_rows(p, l, ctn, sm, lm, l0, lpv);
+            const double piv = l0 - lm * cp[s];
+            if (lead && valid) record_pivot(piv, minpiv, bad);
+            const double iv = 1.0 / piv;
+            cp[s] = lpv * iv;
+            if (lead) Cl[valid ? m : 0] = cp[s];
+            dp[0][s] = ((double)out[s] - lm * dp[0][s]) * iv;
+            line_p[valid ? m : 0] = (T)dp[0][s];
+          }
+        } else if constexpr (kHoistS) {
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
@@ -1080,7 +1098,9 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
           }
         }
       }
-      if constexpr (kHoistS) {
+      if constexpr (kHoistS && NR == 1) {
+        // (applied with the pivots above)
+      } else if constexpr (kHoistS) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int m = line_mode<MY, WPL, KIND>(tl, s, p.ny);
@@ -1104,9 +1124,12 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
   if (lead && (active || WPL > 1)) flush_stats(p, minpiv, bad);
 }
 
+#ifndef CS3D_K2_ATTR
+#define CS3D_K2_ATTR
+#endif
 // grid: (line groups, groups of NR right-hand sides)
 template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
-__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
+__global__ void __launch_bounds__(kBlockY) CS3D_K2_ATTR k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL, ypair<T, MY, WPL, true>()>(p, smem, true);
