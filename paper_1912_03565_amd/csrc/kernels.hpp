@@ -1124,12 +1124,9 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
   if (lead && (active || WPL > 1)) flush_stats(p, minpiv, bad);
 }
 
-#ifndef CS3D_K2_ATTR
-#define CS3D_K2_ATTR
-#endif
 // grid: (line groups, groups of NR right-hand sides)
 template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
-__global__ void __launch_bounds__(kBlockY) CS3D_K2_ATTR k_fwd_y(ProbDev p, int nrhs) {
+__global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL, ypair<T, MY, WPL, true>()>(p, smem, true);
