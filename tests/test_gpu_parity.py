@@ -66,6 +66,9 @@ CASES = [
     ("helm4", 1023, 63, 5),     # fft1024 / fft64
     ("helm4", 63, 1023, 4),     # fft64 / fft1024
     ("helm6", 30, 17, 9),       # dense / dense, ragged tiles
+    ("helm6", 65, 66, 7),       # dense / dense: last RHS tile of 1 column (x-face pass)
+    ("helm6", 67, 70, 8),       # dense / dense: last RHS tile of 3 columns (x faces in the RHS pass)
+    ("helm6", 5, 9, 6),         # dense tiny, x faces through the face pass
     ("cd4", 100, 63, 12),       # dense / fft64
     ("helm4", 63, 50, 7),       # fft64 / dense
     ("helm2", 5, 7, 6),         # dense tiny
