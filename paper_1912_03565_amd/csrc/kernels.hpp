@@ -1230,8 +1230,13 @@ __global__ void __launch_bounds__(kBlockY) k_back_y(ProbDev p, int nrhs) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const cx<T>* tab = y_tables<T, MY, WPL, ypair<T, MY, WPL, false>()>(p, smem, true);
-  const int r0 = blockIdx.y * NR;
-  yback_block<T, MY, WPL, NR, KIND>(p, blockIdx.x, r0, min(NR, nrhs - r0), smem, tab);
+  // work index in XCD order, right-hand-side groups fastest: the workgroups of one line
+  // group (every right-hand side) run at the same time on one XCD and march over the planes
+  // together, so the c' rows they all read come from that XCD's L2 after the first
+  const int nrg = gridDim.y;
+  const int L = xcd_order(linear_block(), gridDim.x * nrg);
+  const int r0 = (L % nrg) * NR;
+  yback_block<T, MY, WPL, NR, KIND>(p, L / nrg, r0, min(NR, nrhs - r0), smem, tab);
 }
 
 // ---------------------------------------------------------------------------
