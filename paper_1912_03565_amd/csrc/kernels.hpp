@@ -1696,7 +1696,10 @@ template <int MY, int WPL = default_wpl<MY>()>
 __global__ void __launch_bounds__(kBlockY) k_back_y_c(ProbDev p) {
   extern __shared__ __align__(16) double smem_raw[];
   const cx<double>* tab = y_tables<double, MY, WPL>(p, smem_raw, true);
-  yback_block_c<MY, WPL>(p, blockIdx.x, blockIdx.y, smem_raw, tab);
+  // work order as in k_back_y: the right-hand sides of a line group side by side on one XCD
+  const int nq = gridDim.y;
+  const int L = xcd_order(linear_block(), gridDim.x * nq);
+  yback_block_c<MY, WPL>(p, L / nq, L % nq, smem_raw, tab);
 }
 
 // ---------------------------------------------------------------------------
