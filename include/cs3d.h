@@ -65,7 +65,7 @@ typedef enum {
   CS3D_E_DEVICE = 3,         /* a HIP call failed */
   CS3D_E_SINGULAR = 4,       /* a zero or non-finite pivot was met (from cs3d_get_stats) */
   CS3D_E_NOTCONVERGED = 5,   /* refinement did not reach its residual target */
-  CS3D_E_UNSUPPORTED = 6,    /* valid request this build cannot serve */
+  CS3D_E_UNSUPPORTED = 6,    /* valid request the library does not serve */
   CS3D_E_WORKSPACE = 7,      /* workspace missing or too small */
   CS3D_E_TOO_LARGE = 8       /* cs3d_solve_static: the solve needs more than its scratch */
 } cs3d_status;
