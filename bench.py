@@ -59,16 +59,43 @@ STAGE_KEYS = ["k_rhs", "k_fwd_x", "k_fwd_y", "k_back_y", "k_inv_x", "k_residual"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp64_helm6_1023cubed_x4rhs.json")
 
 
+def _code_text(src):
+    """C++ source without its comments, whitespace runs collapsed to one blank: what the
+    compiler sees apart from layout.  String and character literals are kept verbatim (a
+    comment marker inside one is not a comment)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash():
-    """sha256 over the HIP sources the kernels are built from."""
+    """sha256 over the code of the HIP sources the kernels are built from (comments and
+    layout excluded, so an edit of a comment keeps the counter runs valid)."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1912_03565_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                h.update(name.encode() + b"\0" + _code_text(fh.read()).encode())
     return h.hexdigest()
 
 

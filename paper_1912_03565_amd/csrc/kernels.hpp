@@ -2,9 +2,11 @@
 //
 //  K0 rhs     : RHS operator of the scheme (Sections 3.2-3.5) + z-face lift, written as
 //               the interior array F (into the caller's output buffer).  Workgroups
-//               march along z over a 64 x 16 tile, keeping five planes (with a halo of
-//               two) in LDS, so f is read from HBM about once.
-//  K1 fwd_x   : DST-I along x of 16 x-lines of F per workgroup; the results are
+//               march along z over a 64 x 64 tile (64 x 16 in the batch), with a ring of
+//               four halo planes in LDS and the thread's own column of five planes in
+//               registers, so f is read from HBM about once; the corrections on the
+//               faces of the box follow in small per-axis passes.
+//  K1 fwd_x   : DST-I along x of 8 x-lines of F per workgroup; the results are
 //               transposed through LDS and stored as y-lines G[l][n][j] (j fastest).
 //  K2 fwd_y   : one line group (one or two wavefronts) per x-mode n marches l = 1..N_z:
 //               DST-I along y of G[l][n][:], modal eigenvalues lambda^{-,0,+} built on the
