@@ -240,7 +240,9 @@ cs3d_status cs3d_reset_timers(cs3d_plan plan);
  * cs3d_batch_autotune time the candidates on the caller's data and keep the fastest.
  * zchunk, xpersist, yrhs, order and graph do not change the arithmetic (results are bitwise
  * the same for every value); ywpl selects another radix split of the y-line FFT, which
- * changes the rounding of the transform only. */
+ * changes the rounding of the transform only, and pack runs other kernels with the same
+ * arithmetic per line, whose results agree to rounding (the compiler may fuse multiplies
+ * and adds differently there). */
 typedef struct {
   int zchunk;    /* z-planes per workgroup of the z-marching passes (RHS operator and, on the
                     mixed path, the FP64 residual): 8..512, default 32, for nz >= 512
@@ -259,12 +261,16 @@ typedef struct {
                     each read of c'; transform sizes whose lanes hold 16 modes use 1. */
   int xwpl;      /* x passes of a plan where N_x+1 is 512 or 1024: waves per line, 1 or 2
                     (1024 threads per workgroup, half a line per lane); other sizes use 1 */
+  int pack;      /* batches: 1 = in the x and y passes a wave carries 4 lines of a 64-point
+                    or 2 lines of a 128-point transform (the lanes its FFT uses), 0 = one
+                    line per wave (default: the packed kernels hold more registers, which
+                    a batch of large members alone does not repay) */
 } cs3d_tuning;
 
 /* Current launch-shape choices of a plan.  Errors: E_INVAL (NULL argument). */
 cs3d_status cs3d_get_tuning(cs3d_plan plan, cs3d_tuning* out);
 
-/* Set the launch-shape choices of a plan (order and graph are ignored).
+/* Set the launch-shape choices of a plan (order, graph and pack are ignored).
  * Errors: E_INVAL (NULL argument or a field out of range). */
 cs3d_status cs3d_set_tuning(cs3d_plan plan, const cs3d_tuning* tuning);
 
@@ -318,15 +324,15 @@ cs3d_status cs3d_batch_get_stats(cs3d_batch batch, cs3d_stats* out_stats);
  * timing fields are those of the batch).  Errors: E_INVAL (index out of range). */
 cs3d_status cs3d_batch_member_stats(cs3d_batch batch, int i, cs3d_stats* out_stats);
 
-/* Launch-shape choices of a batch (zchunk, order, graph; xpersist, ywpl and yrhs are
- * ignored: batch passes are always resident, use the default waves per line and carry the
- * one right-hand side of each member).  Setting them
+/* Launch-shape choices of a batch (zchunk, order, graph, pack; xpersist, ywpl, yrhs and
+ * xwpl are ignored: batch passes are always resident, use the default waves per line and
+ * carry the one right-hand side of each member).  Setting them
  * rebuilds the work lists and drops the captured graph.
  * Errors: E_INVAL (NULL argument or a field out of range), E_DEVICE. */
 cs3d_status cs3d_batch_get_tuning(cs3d_batch batch, cs3d_tuning* out);
 cs3d_status cs3d_batch_set_tuning(cs3d_batch batch, const cs3d_tuning* tuning);
 
-/* As cs3d_autotune for a batch: times zchunk and order candidates with per-pass timing,
+/* As cs3d_autotune for a batch: times zchunk, pack and order candidates with per-pass timing,
  * then enables graph replay.  The arguments are those of cs3d_batch_solve.
  * Errors: as cs3d_batch_solve; E_INVAL for reps < 1. */
 cs3d_status cs3d_batch_autotune(cs3d_batch batch, const double* const* dev_f, double* const* dev_u,

@@ -66,10 +66,19 @@ __global__ void kb_stats_reset(unsigned long long* s, int n) {
   s[e] = w == 0 ? 0x7FEFFFFFFFFFFFFFull : 0ull;  // bits of DBL_MAX, then zeros
 }
 
-// x-pass items: tiles of 8 y-lines of one plane
-__host__ __device__ inline int x_items(int ldy, int nz) { return (ldy / kTileJ) * nz; }
+// Packed lines (batch tuning `pack`): the FFT of 64 or 128 points keeps M/4 lanes busy
+// (4 complex values each), so with packing a wave carries 256/M lines of such a member in
+// the x and y passes instead of one; the arithmetic of every line is unchanged.
+__host__ __device__ constexpr int pack_lines(int f, int pack) { return (pack && (f == 64 || f == 128)) ? 256 / f : 1; }
+// x-pass items: tiles of 8 P y-lines of one plane (P lines per wave); the last tile of a
+// plane may reach past the row length ldy, whose positions it neither reads nor writes
+__host__ __device__ inline int x_tile_lines(int fx, int pack) { return kTileJ * pack_lines(fx, pack); }
+__host__ __device__ inline int x_items(int ldy, int nz, int tj) { return ((ldy + tj - 1) / tj) * nz; }
 // y-pass items: groups of LPB lines (x-modes)
 __host__ __device__ inline int y_items(int nx, int lpb) { return (nx + lpb - 1) / lpb; }
+__host__ __device__ inline int y_lanes(int fy, int pack) {
+  return pack_lines(fy, pack) > 1 ? fy / 4 : 64 * (fy == 1024 ? default_wpl<1024>() : 1);
+}
 // RHS items: 64 x 16 tiles times z-chunks
 __host__ __device__ inline int rhs_items(int nx, int ny, int nz, int zchunk) {
   return ((nx + kRX - 1) / kRX) * ((ny + kRYBatch - 1) / kRYBatch) * ((nz + zchunk - 1) / zchunk);
@@ -112,71 +121,99 @@ __global__ void __launch_bounds__(kRThreadsBatch) kb_rhs(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
-// x passes: the twiddle tables sit at the start of the LDS, the line buffers after them
+// x passes: the twiddle tables sit at the start of the LDS, the line buffers after them.
+// An item is a tile of TJ = 8 P y-lines of one plane: wave w transforms tile rows
+// w P .. w P + P - 1 (lane group sub = lane / LL, LL lanes per line), and the tile is
+// transposed through the LDS (row stride tile_stride(nx, TJ)).
 // ---------------------------------------------------------------------------
-template <typename T, int MX>
+struct XItem {
+  int jt, l, row, j, jmax;  // tile, plane, tile row of this lane group, its line, rows inside ldy
+  bool active;
+};
+
+template <int P>
+__device__ __forceinline__ XItem decode_xitem(const ProbDev& p, int t, int row) {
+  constexpr int TJ = kTileJ * P;
+  const int njt = (p.ldy + TJ - 1) / TJ;
+  XItem x;
+  x.jt = t % njt;
+  x.l = t / njt + 1;
+  x.row = row;
+  x.j = x.jt * TJ + row;
+  x.jmax = min(TJ, p.ldy - x.jt * TJ);
+  x.active = x.j >= 1 && x.j <= p.ny;
+  return x;
+}
+
+template <typename T, int MX, int P>
 __device__ __forceinline__ void xfwd_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
   constexpr int NS = Tx<MX, 1>::NS;
+  constexpr int TJ = kTileJ * P, LL = 64 / P;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = lane / LL, tl = lane % LL;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
-  const int ts = tile_stride(p.nx);
-  T* buf = lines + w * bufn;
-  const XTile x = decode_xtile(p, t, w);
+  const int ts = tile_stride(p.nx, TJ);
+  const XItem x = decode_xitem<P>(p, t, w * P + sub);
+  T* buf = lines + x.row * bufn;
   if (x.active) {
     const double* Fr = p.F + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
-    if (lane == 0) buf[0] = (T)0;
-    for (int i = 1 + lane; i <= p.nx; i += 64) buf[i] = (T)Fr[i - 1];
+    if (tl == 0) buf[0] = (T)0;
+    for (int i = 1 + tl; i <= p.nx; i += LL) buf[i] = (T)Fr[i - 1];
   }
   __syncthreads();
   T out[NS];
-  if (x.active) line_dst<T, MX, 1>(buf, p.nx, out, lane, tab, p.sinx);
+  if (x.active) line_dst<T, MX, 1>(buf, p.nx, out, tl, tab, p.sinx);
   __syncthreads();
   if (x.active) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int n = line_mode<MX, 1>(lane, s, p.nx);
-      if (n > 0) lines[w * ts + n] = out[s];
+      const int n = line_mode<MX, 1>(tl, s, p.nx);
+      if (n > 0) lines[x.row * ts + n] = out[s];
     }
   } else {
-    for (int n = 1 + lane; n <= p.nx; n += 64) lines[w * ts + n] = (T)0;
+    for (int n = 1 + tl; n <= p.nx; n += LL) lines[x.row * ts + n] = (T)0;
   }
   __syncthreads();
-  T* G = reinterpret_cast<T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
-  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
-    const int n0 = idx / kTileJ, jj = idx % kTileJ;
-    G[(long long)n0 * p.ldy + jj] = lines[jj * ts + n0 + 1];
+  T* G = reinterpret_cast<T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * TJ;
+  for (int idx = threadIdx.x; idx < p.nx * TJ; idx += blockDim.x) {
+    const int n0 = idx / TJ, jj = idx % TJ;
+    if (jj < x.jmax) G[(long long)n0 * p.ldy + jj] = lines[jj * ts + n0 + 1];
   }
   __syncthreads();
 }
 
-template <typename T, int MX>
+template <typename T, int MX, int P>
 __device__ __forceinline__ void xinv_item(const ProbDev& p, int t, T* lines, const cx<T>* tab) {
   constexpr int NS = Tx<MX, 1>::NS;
+  constexpr int TJ = kTileJ * P, LL = 64 / P;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = lane / LL, tl = lane % LL;
   const int bufn = line_buf_elems<T, MX, 1>(p.nx);
-  const int ts = tile_stride(p.nx);
-  T* buf = lines + w * bufn;
-  const XTile x = decode_xtile(p, t, w);
-  const T* G = reinterpret_cast<const T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
-  for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
-    const int n0 = idx / kTileJ, jj = idx % kTileJ;
-    lines[jj * ts + n0 + 1] = G[(long long)n0 * p.ldy + jj];
+  const int ts = tile_stride(p.nx, TJ);
+  const XItem x = decode_xitem<P>(p, t, w * P + sub);
+  T* buf = lines + x.row * bufn;
+  const T* G = reinterpret_cast<const T*>(p.G) + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * TJ;
+  for (int idx = threadIdx.x; idx < p.nx * TJ; idx += blockDim.x) {
+    const int n0 = idx / TJ, jj = idx % TJ;
+    lines[jj * ts + n0 + 1] = jj < x.jmax ? G[(long long)n0 * p.ldy + jj] : (T)0;
   }
   __syncthreads();
   T out[NS];
-  line_dst<T, MX, 1, true>(buf, p.nx, out, lane, tab, p.sinx, lines + w * ts);
+  line_dst<T, MX, 1, true>(buf, p.nx, out, tl, tab, p.sinx, lines + x.row * ts);
   if (x.active) {
     double* u = p.u + (long long)p.nx * ((x.j - 1) + (long long)p.ny * (x.l - 1));
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      const int i = line_mode<MX, 1>(lane, s, p.nx);
+      const int i = line_mode<MX, 1>(tl, s, p.nx);
       if (i > 0) u[i - 1] = p.scale * (double)out[s];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int MAXM, bool DENSE, bool FWD>
+// PACK: lines of 64- and 128-point transforms packed 4 or 2 to a wave (a kernel of its own,
+// so the unpacked kernel keeps its register budget)
+template <typename T, int MAXM, bool DENSE, bool FWD, bool PACK>
 __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -198,8 +235,9 @@ __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
     }
     dispatch_m<MAXM, DENSE>(p.fx, [&](auto mc) {
       constexpr int MM = decltype(mc)::value;
-      if constexpr (FWD) xfwd_item<T, MM>(p, t, lines, tab);
-      else xinv_item<T, MM>(p, t, lines, tab);
+      constexpr int P = pack_lines(MM, PACK);
+      if constexpr (FWD) xfwd_item<T, MM, P>(p, t, lines, tab);
+      else xinv_item<T, MM, P>(p, t, lines, tab);
     });
   }
 }
@@ -207,7 +245,7 @@ __global__ void __launch_bounds__(64 * kTileJ) kb_x(BatchArgs b) {
 // ---------------------------------------------------------------------------
 // y passes (default waves per line of each size)
 // ---------------------------------------------------------------------------
-template <typename T, int MAXM, bool DENSE, bool FWD>
+template <typename T, int MAXM, bool DENSE, bool FWD, bool PACK>
 __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
   extern __shared__ __align__(16) double smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -229,8 +267,9 @@ __global__ void __launch_bounds__(kBlockY) kb_y(BatchArgs b) {
     }
     dispatch_m<MAXM, DENSE>(p.fy, [&](auto mc) {
       constexpr int MM = decltype(mc)::value;
-      if constexpr (FWD) yfwd_block<T, MM, default_wpl<MM>(), 1>(p, g, 0, 1, lines, tab);
-      else yback_block<T, MM, default_wpl<MM>(), 1>(p, g, 0, 1, lines, tab);
+      constexpr bool PK = PACK && (MM == 64 || MM == 128);
+      if constexpr (FWD) yfwd_block<T, MM, default_wpl<MM>(), 1, kDst, false, PK>(p, g, 0, 1, lines, tab);
+      else yback_block<T, MM, default_wpl<MM>(), 1, kDst, PK>(p, g, 0, 1, lines, tab);
     });
   }
 }

@@ -57,6 +57,7 @@ struct Tuning {
   int graph = 1;         // batches: captured graph replay
   int yrhs = 1;          // right-hand sides per y-pass workgroup (1, 2 or 4)
   int xwpl = 1;          // waves per x-line where the FFT allows two (M >= 512)
+  int pack = 0;          // batches: lines of 64- and 128-point transforms packed to a wave
 };
 
 struct cs3d_plan_s {
@@ -1191,7 +1192,8 @@ extern "C" const char* cs3d_version(void) { return "cs3d 0.1 (gfx950)"; }
 static bool tuning_ok(const cs3d_tuning* t) {
   return t && t->zchunk >= 8 && t->zchunk <= 512 && (t->xpersist == 0 || t->xpersist == 1) &&
          (t->ywpl == 1 || t->ywpl == 2) && (t->order == 0 || t->order == 1) && (t->graph == 0 || t->graph == 1) &&
-         (t->yrhs == 1 || t->yrhs == 2 || t->yrhs == 4) && (t->xwpl == 1 || t->xwpl == 2);
+         (t->yrhs == 1 || t->yrhs == 2 || t->yrhs == 4) && (t->xwpl == 1 || t->xwpl == 2) &&
+         (t->pack == 0 || t->pack == 1);
 }
 
 static void tuning_out(const Tuning& t, cs3d_tuning* o) {
@@ -1202,6 +1204,7 @@ static void tuning_out(const Tuning& t, cs3d_tuning* o) {
   o->graph = t.graph;
   o->yrhs = t.yrhs;
   o->xwpl = t.xwpl;
+  o->pack = t.pack;
 }
 
 extern "C" cs3d_status cs3d_get_tuning(cs3d_plan p, cs3d_tuning* out) {
@@ -1328,7 +1331,6 @@ static int list_stride(const cs3d_batch b) { return 2 * b->n + 1; }
 // relative cost of one line transform of N points (FFT of length f, or dense sums)
 static double line_cost(int f, int N) { return f ? f * std::log2((double)f) : 0.25 * (double)N * N; }
 
-static int y_wpl(int fy) { return fy == 1024 ? 2 : 1; }
 
 // LDS elements (doubles) of one line buffer of the y passes, as line_buf_elems for T = double
 // with the default waves per line; at 1024 points the larger of the forward pass's buffer
@@ -1358,21 +1360,28 @@ static size_t line_elems_x(int f, int N) {
 template <int MAXM, bool DENSE>
 static cs3d_status batch_grids_t(cs3d_batch b) {
   size_t lx = 0, ly = 0;
+  const int pk = b->tune.pack;
   for (cs3d_plan q : b->plans) {
-    const size_t ts = (size_t)tile_stride(q->d.nx);
+    const int tj = x_tile_lines(q->fx, pk);
+    const size_t ts = (size_t)tile_stride(q->d.nx, tj);
     const size_t bx = line_elems_x(q->fx, q->d.nx);
-    lx = std::max(lx, (size_t)kTileJ * std::max(bx, ts) * 8);
-    ly = std::max(ly, (size_t)(kBlockY / (64 * y_wpl(q->fy))) * line_elems(q->fy, q->d.ny) * 8);
+    lx = std::max(lx, (size_t)tj * std::max(bx, ts) * 8);
+    ly = std::max(ly, (size_t)(kBlockY / y_lanes(q->fy, pk)) * line_elems(q->fy, q->d.ny) * 8);
   }
   const size_t tw = (size_t)tw_entries<MAXM>() * sizeof(cx<double>);
   b->lds[kPassRhs] = 0;
   b->lds[kPassXf] = b->lds[kPassXi] = tw + lx;
   b->lds[kPassYf] = b->lds[kPassYb] = tw + ly;
-  const void* kern[kPasses] = {reinterpret_cast<const void*>(kb_rhs),
-                               reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, true>),
-                               reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, true>),
-                               reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, false>),
-                               reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, false>)};
+  const void* kern[kPasses] = {
+      reinterpret_cast<const void*>(kb_rhs),
+      pk ? reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, true, true>)
+         : reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, true, false>),
+      pk ? reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, true, true>)
+         : reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, true, false>),
+      pk ? reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, false, true>)
+         : reinterpret_cast<const void*>(kb_y<double, MAXM, DENSE, false, false>),
+      pk ? reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, false, true>)
+         : reinterpret_cast<const void*>(kb_x<double, MAXM, DENSE, false, false>)};
   const int threads[kPasses] = {kRThreadsBatch, 64 * kTileJ, kBlockY, kBlockY, 64 * kTileJ};
   for (int k = 0; k < kPasses; ++k) {
     if (b->lds[k] > 160 * 1024) return CS3D_E_UNSUPPORTED;
@@ -1401,12 +1410,13 @@ static cs3d_status batch_prepare(cs3d_batch b) {
           break;
         case kPassXf:
         case kPassXi:
-          items[i] = x_items(q->ldy, nz);
+          // (a packed item holds more lines on more lanes, in about the time of an unpacked one)
+          items[i] = x_items(q->ldy, nz, x_tile_lines(q->fx, b->tune.pack));
           cost[i] = line_cost(q->fx, nx);
           break;
         default:
-          items[i] = y_items(nx, kBlockY / (64 * y_wpl(q->fy)));
-          cost[i] = nz * line_cost(q->fy, ny) / y_wpl(q->fy);
+          items[i] = y_items(nx, kBlockY / y_lanes(q->fy, b->tune.pack));
+          cost[i] = nz * line_cost(q->fy, ny) * 64 / y_lanes(q->fy, 0);
           break;
       }
     }
@@ -1433,7 +1443,7 @@ static cs3d_status batch_prepare(cs3d_batch b) {
   return CS3D_OK;
 }
 
-template <int MAXM, bool DENSE>
+template <int MAXM, bool DENSE, bool PACK>
 static hipError_t batch_pass_t(const cs3d_batch b, int pass, hipStream_t s) {
   if (b->total[pass] == 0) return hipSuccess;
   const int* lst = b->dlist + (size_t)pass * list_stride(b);
@@ -1441,12 +1451,25 @@ static hipError_t batch_pass_t(const cs3d_batch b, int pass, hipStream_t s) {
   const dim3 g(b->grid[pass]);
   switch (pass) {
     case kPassRhs: hipLaunchKernelGGL(kb_rhs, g, dim3(kRThreadsBatch), 0, s, a); break;
-    case kPassXf: hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, true>), g, dim3(64 * kTileJ), b->lds[pass], s, a); break;
-    case kPassYf: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, true>), g, dim3(kBlockY), b->lds[pass], s, a); break;
-    case kPassYb: hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, false>), g, dim3(kBlockY), b->lds[pass], s, a); break;
-    default: hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, false>), g, dim3(64 * kTileJ), b->lds[pass], s, a); break;
+    case kPassXf:
+      hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, true, PACK>), g, dim3(64 * kTileJ), b->lds[pass], s, a);
+      break;
+    case kPassYf:
+      hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, true, PACK>), g, dim3(kBlockY), b->lds[pass], s, a);
+      break;
+    case kPassYb:
+      hipLaunchKernelGGL((kb_y<double, MAXM, DENSE, false, PACK>), g, dim3(kBlockY), b->lds[pass], s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((kb_x<double, MAXM, DENSE, false, PACK>), g, dim3(64 * kTileJ), b->lds[pass], s, a);
+      break;
   }
   return hipGetLastError();
+}
+
+static hipError_t batch_pass(const cs3d_batch b, int pass, hipStream_t s) {
+  if (b->general) return b->tune.pack ? batch_pass_t<1024, true, true>(b, pass, s) : batch_pass_t<1024, true, false>(b, pass, s);
+  return b->tune.pack ? batch_pass_t<256, false, true>(b, pass, s) : batch_pass_t<256, false, false>(b, pass, s);
 }
 
 // statistics reset + the five passes; with events between the passes when `marks`
@@ -1456,8 +1479,7 @@ static hipError_t batch_launch(const cs3d_batch b, hipStream_t s, bool marks) {
   hipLaunchKernelGGL(kb_stats_reset, dim3((words + 255) / 256), dim3(256), 0, s, b->dstats, b->n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int k = 0; k < kPasses; ++k) {
-    if ((e = b->general ? batch_pass_t<1024, true>(b, k, s) : batch_pass_t<256, false>(b, k, s)) != hipSuccess)
-      return e;
+    if ((e = batch_pass(b, k, s)) != hipSuccess) return e;
     if (marks && (e = hipEventRecord(b->ev[k + 1], s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1684,10 +1706,11 @@ extern "C" cs3d_status cs3d_batch_get_tuning(cs3d_batch b, cs3d_tuning* out) {
 extern "C" cs3d_status cs3d_batch_set_tuning(cs3d_batch b, const cs3d_tuning* t) {
   if (!b || !tuning_ok(t)) return CS3D_E_INVAL;
   if (b->last_stream && hipStreamSynchronize(b->last_stream) != hipSuccess) return CS3D_E_DEVICE;
-  const bool lists = t->zchunk != b->tune.zchunk || t->order != b->tune.order;
+  const bool lists = t->zchunk != b->tune.zchunk || t->order != b->tune.order || t->pack != b->tune.pack;
   b->tune.zchunk = t->zchunk;
   b->tune.order = t->order;
   b->tune.graph = t->graph;
+  b->tune.pack = t->pack;
   if (lists) {
     b->ready = false;
     b->have_ptrs = false;  // zchunk is in the descriptors
@@ -1734,6 +1757,20 @@ extern "C" cs3d_status cs3d_batch_autotune(cs3d_batch b, const double* const* f,
     }
   }
   best.zchunk = bz;
+  // packed lines shape the transform passes (x and y, both directions)
+  bt = INFINITY;
+  int bp = best.pack;
+  for (int pk : {0, 1}) {
+    cs3d_tuning t = best;
+    t.pack = pk;
+    if ((st = run(t, stage)) != CS3D_OK) return st;
+    const double tt = stage[kPassXf] + stage[kPassYf] + stage[kPassYb] + stage[kPassXi];
+    if (tt < bt) {
+      bt = tt;
+      bp = pk;
+    }
+  }
+  best.pack = bp;
   // the member order shapes every pass
   bt = INFINITY;
   int bo = best.order;

@@ -137,11 +137,11 @@ __host__ __device__ constexpr int tw_bytes() {
   return M ? tw_entries<M>() * (int)sizeof(cx<T>) : 0;
 }
 
-// row stride (>= nx + 1, = 32 / kTileJ mod 32) of the K1/K4 transpose tile: the transposed
-// accesses (kTileJ rows x 32 / kTileJ columns per half-wave) then hit 32 distinct bank
-// pairs, and a row starts 16-byte aligned
-__host__ __device__ constexpr int tile_stride(int nx) {
-  return ((nx + 1 - 32 / kTileJ + 31) / 32) * 32 + 32 / kTileJ;
+// row stride (>= nx + 1, = 32 / tj mod 32) of the K1/K4 transpose tile of tj (8, 16 or 32)
+// rows: the transposed accesses (tj rows x 32 / tj columns per half-wave) then hit 32
+// distinct bank pairs
+__host__ __device__ constexpr int tile_stride(int nx, int tj = kTileJ) {
+  return ((nx + 1 - 32 / tj + 31) / 32) * 32 + 32 / tj;
 }
 
 // ---------------------------------------------------------------------------
@@ -919,10 +919,22 @@ __device__ __forceinline__ void flush_stats(const ProbDev& p, double minpiv, uns
 template <int MY>
 constexpr int default_wpl() { return MY == 1024 ? 2 : 1; }
 
-template <int MY, int WPL_ = default_wpl<MY>(), int KIND = kDst>
+// PACK: the lines of 64- and 128-point transforms take the M/4 lanes their FFT uses, so
+// a wave carries 4 or 2 lines (batches; see the batch tuning); else each line has whole waves
+template <int MY, int WPL, bool PACK>
+__host__ __device__ constexpr int ycfg_lanes() {
+  if constexpr (PACK) {
+    return FftGeom<MY, 1>::L;
+  } else {
+    return 64 * WPL;
+  }
+}
+
+template <int MY, int WPL_ = default_wpl<MY>(), int KIND = kDst, bool PACK = false>
 struct YCfg {
+  static_assert(!PACK || ((MY == 64 || MY == 128) && WPL_ == 1 && KIND == kDst), "packed lines: 64 or 128 points");
   static constexpr int WPL = WPL_;
-  static constexpr int LANES = 64 * WPL;
+  static constexpr int LANES = ycfg_lanes<MY, WPL_, PACK>();
   static constexpr int LPB = kBlockY / LANES;  // lines (x-modes) per workgroup
   static constexpr int NS = Tx<MY, WPL, KIND>::NS;
   // line values loaded per lane (positions 0..N; N = M + 1 for the cosine transform)
@@ -967,17 +979,19 @@ __device__ __forceinline__ cx<T>* y_tables(const ProbDev& p, T* smem, bool load)
 // 3.6 does not depend on the right-hand side).  The workgroup of r0 = 0 stores c' and
 // records the pivots.
 // ROBIN: Robin z faces, whose first and last modal rows change (robin_rows)
-template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool ROBIN = false, bool PACK = false>
 __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
-  using C = YCfg<MY, WPL, KIND>;
+  using C = YCfg<MY, WPL, KIND, PACK>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY, WPL, ypair<T, MY, WPL, true>()>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;
   const int n = g * C::LPB + line + 1;
   const bool active = n <= p.nx;
-  if constexpr (WPL == 1) {
+  if constexpr (WPL == 1 && !PACK) {
     if (!active) return;  // no workgroup barrier below for single-wave lines
   }
+  // (packed lines share a wave and its pivot reduction at the end: an inactive one runs on
+  // zeros like the inactive lines of two-wave lines)
   T* buf = smem + line * bufn;
   const double ctn = active ? p.ctx[n - 1] : 0.0;
   // s_m of each slot's mode is the same on every plane: held in registers where they allow
@@ -1123,7 +1137,7 @@ __device__ __forceinline__ void yfwd_block(const ProbDev& p, int g, int r0, int 
       line_sync<WPL>();
     }
   }
-  if (lead && (active || WPL > 1)) flush_stats(p, minpiv, bad);
+  if (lead && (active || WPL > 1 || PACK)) flush_stats(p, minpiv, bad);
 }
 
 // grid: (line groups, groups of NR right-hand sides)
@@ -1140,9 +1154,9 @@ __global__ void __launch_bounds__(kBlockY) k_fwd_y(ProbDev p, int nrhs) {
 // K3: back substitution + inverse DST along y, the right-hand sides of a workgroup
 // sharing each read of c'.
 // ---------------------------------------------------------------------------
-template <typename T, int MY, int WPL, int NR, int KIND = kDst>
+template <typename T, int MY, int WPL, int NR, int KIND = kDst, bool PACK = false>
 __device__ __forceinline__ void yback_block(const ProbDev& p, int g, int r0, int nr, T* smem, const cx<T>* tab) {
-  using C = YCfg<MY, WPL, KIND>;
+  using C = YCfg<MY, WPL, KIND, PACK>;
   constexpr int NS = C::NS;
   const int bufn = line_buf_elems<T, MY, WPL, ypair<T, MY, WPL, false>()>(p.ny);
   const int line = threadIdx.x / C::LANES, tl = threadIdx.x % C::LANES;

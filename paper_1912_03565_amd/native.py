@@ -67,7 +67,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("zchunk", ctypes.c_int), ("xpersist", ctypes.c_int), ("ywpl", ctypes.c_int),
         ("order", ctypes.c_int), ("graph", ctypes.c_int), ("yrhs", ctypes.c_int),
-        ("xwpl", ctypes.c_int),
+        ("xwpl", ctypes.c_int), ("pack", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -7,7 +7,8 @@ precision and number of right-hand sides.
 
 The cache file is CS3D_TUNE_CACHE, else ~/.cache/cs3d/tuning.json.  CS3D_AUTOTUNE=0
 turns tuning off (the defaults are kept and nothing is written).  The choices change
-launch shapes only: results are bitwise the same for every entry.
+launch shapes: results are bitwise the same for every entry, except that another radix
+split of a y-line (ywpl, plans) and packed lines (pack, batches) change the rounding only.
 """
 import hashlib
 import json

@@ -78,12 +78,6 @@ def _check_members(probs, us, label):
     return res
 
 
-# members covering every transform path of the general kernel variant: dense sine sums,
-# FFT lengths 64 ... 1024, single planes, ragged tiles, every scheme
-MIXED = [("helm6", 30, 17, 9), ("cd4", 100, 63, 12), ("helm4", 511, 63, 6), ("helm4", 63, 1023, 4),
-         ("helm2", 5, 7, 6), ("cd4", 3, 2, 1), ("helm6", 63, 127, 33), ("helm4", 127, 63, 20)]
-
-
 def test_batch_general_variant_matches_oracle(cs3d):
     probs = [WL.noise_problem(nx, ny, nz, s, seed=500 + i, boundary=False)
              for i, (s, nx, ny, nz) in enumerate(MIXED)]
@@ -174,7 +168,58 @@ def test_batch_tuning_is_bitwise_neutral(cs3d):
             assert torch.equal(u, r), t
     best, ms = b.autotune(fs, reps=1)
     assert best["graph"] == 1 and best["zchunk"] in (16, 32, 64, 128) and ms > 0
+    b.set_tuning({"pack": 0})  # (packed lines run other kernels: test_packed_lines_*)
     for u, r in zip(b.solve(fs), ref):
+        assert torch.equal(u, r)
+    b.close()
+
+
+# Packed lines (tuning "pack"): x-pass tiles of 32 (64-point) or 16 (128-point) lines, some
+# reaching past the row length (ldy 16 and 48 against 32-line tiles); y-pass groups of 16
+# or 8 lines whose last group leaves part of a wave inactive (N_x = 37, 99)
+PACKED_GENERAL = [("helm6", 63, 63, 31), ("helm4", 63, 15, 9), ("helm6", 63, 47, 8), ("cd4", 127, 47, 12),
+                  ("helm4", 37, 63, 10), ("cd4", 99, 127, 12), ("helm2", 127, 79, 7), ("helm4", 255, 63, 5)]
+PACKED_DEFAULT = [("helm6", 63, 63, 31), ("helm4", 127, 255, 20), ("cd4", 255, 63, 9), ("helm6", 63, 127, 17)]
+
+
+@pytest.mark.parametrize("members", [PACKED_GENERAL, PACKED_DEFAULT], ids=["general", "default"])
+def test_packed_lines_match_unpacked_and_oracle(cs3d, members):
+    """A wave carrying 4 lines of a 64-point or 2 of a 128-point transform (batch tuning
+    pack = 1) runs the same arithmetic per line as one line per wave, compiled into other
+    kernels: the results agree to rounding (relative 1e-14 element by element), in eager
+    launches and in graph replays (each replay bitwise equal to the first packed solve),
+    with the same pivot statistics; every member also against the oracle."""
+    probs = [WL.noise_problem(nx, ny, nz, s, seed=1300 + i, boundary=False)
+             for i, (s, nx, ny, nz) in enumerate(members)]
+    print("batch of", [p.name for p in probs], flush=True)
+    b = _batch(cs3d, probs)
+    fs = [p.f[0].to(DEV) for p in probs]
+    b.set_tuning({"pack": 0, "graph": 0})
+    ref = [u.clone() for u in b.solve(fs)]
+    piv0 = [b.member_stats(i)["min_abs_pivot"] for i in range(len(probs))]
+    packed = None
+    for graph in (0, 1):
+        b.set_tuning({"pack": 1, "graph": graph})
+        assert b.tuning()["pack"] == 1
+        for rep in range(2):
+            us = b.solve(fs)
+            if packed is None:
+                packed = [u.clone() for u in us]
+                for p, u, r in zip(probs, us, ref):
+                    d = (u - r).abs().max().item() / max(r.abs().max().item(), 1e-300)
+                    print(f"  {p.name}: packed vs unpacked max rel diff {d:.2e}"
+                          f"{' (bitwise)' if torch.equal(u, r) else ''}", flush=True)
+                    assert d < 1e-14, (p.name, d)
+            for p, u, r in zip(probs, us, packed):
+                assert torch.equal(u, r), (p.name, graph, rep)
+        assert b.stats()["bad_pivots"] == 0
+        piv = [b.member_stats(i)["min_abs_pivot"] for i in range(len(probs))]
+        assert all(abs(a - c) <= 1e-12 * c for a, c in zip(piv, piv0)), (piv, piv0)
+    _check_members(probs, us, "packed lines")
+    best, ms = b.autotune(fs, reps=1)
+    assert best["pack"] in (0, 1) and best["graph"] == 1 and ms > 0
+    print(f"  autotune: pack {best['pack']}, {ms:.3f} ms per solve", flush=True)
+    for u, r in zip(b.solve(fs), packed if best["pack"] else ref):
         assert torch.equal(u, r)
     b.close()
 
