@@ -72,13 +72,24 @@ __global__ void kb_stats_reset(unsigned long long* s, int n) {
 __host__ __device__ constexpr int pack_lines(int f, int pack) { return (pack && (f == 64 || f == 128)) ? 256 / f : 1; }
 // x-pass items: tiles of 8 P y-lines of one plane (P lines per wave); the last tile of a
 // plane may reach past the row length ldy, whose positions it neither reads nor writes
-__host__ __device__ inline int x_tile_lines(int fx, int pack) { return kTileJ * pack_lines(fx, pack); }
+__host__ __device__ constexpr int x_tile_lines(int fx, int pack) { return kTileJ * pack_lines(fx, pack); }
 __host__ __device__ inline int x_items(int ldy, int nz, int tj) { return ((ldy + tj - 1) / tj) * nz; }
 // y-pass items: groups of LPB lines (x-modes)
 __host__ __device__ inline int y_items(int nx, int lpb) { return (nx + lpb - 1) / lpb; }
-__host__ __device__ inline int y_lanes(int fy, int pack) {
+// lanes per line of a y pass (the host's work lists and LDS sizes use it; the kernels
+// take it from YCfg, which the assertions below tie to it)
+__host__ __device__ constexpr int y_lanes(int fy, int pack) {
   return pack_lines(fy, pack) > 1 ? fy / 4 : 64 * (fy == 1024 ? default_wpl<1024>() : 1);
 }
+static_assert(y_lanes(64, 1) == YCfg<64, 1, kDst, true>::LANES && y_lanes(128, 1) == YCfg<128, 1, kDst, true>::LANES,
+              "packed y lanes");
+static_assert(y_lanes(0, 0) == YCfg<0>::LANES && y_lanes(64, 0) == YCfg<64>::LANES &&
+                  y_lanes(256, 1) == YCfg<256>::LANES && y_lanes(512, 1) == YCfg<512>::LANES &&
+                  y_lanes(1024, 1) == YCfg<1024>::LANES,
+              "y lanes of the default waves per line");
+static_assert(x_tile_lines(64, 1) == 4 * kTileJ && x_tile_lines(128, 1) == 2 * kTileJ && x_tile_lines(256, 1) == kTileJ &&
+                  x_tile_lines(64, 0) == kTileJ,
+              "x tile lines");
 // RHS items: 64 x 16 tiles times z-chunks
 __host__ __device__ inline int rhs_items(int nx, int ny, int nz, int zchunk) {
   return ((nx + kRX - 1) / kRX) * ((ny + kRYBatch - 1) / kRYBatch) * ((nz + zchunk - 1) / zchunk);
