@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI (no GPU needed: nothing here launches a kernel).
 
 * the library loads and exports every entry point declared in include/cs3d.h,
-* argument validation rejects bad descriptions before touching the device.
+* argument validation rejects bad descriptions before touching the device,
+* the ctypes mirrors of the ABI structs match the header (names, offsets, sizes).
 """
 import ctypes
 import os
@@ -202,3 +203,55 @@ def test_neumann_sides_validation(N, case):
     plan = ctypes.c_void_p()
     assert N.lib.cs3d_plan_create(ctypes.byref(d), None, ctypes.byref(plan)) == want
     assert not plan.value
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of cs3d_desc, cs3d_stats and cs3d_tuning (native.py) have the
+    field names, offsets and sizes the C compiler gives the structs of include/cs3d.h
+    (a host program built with gcc prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_1912_03565_amd import native as NM
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    structs = {"cs3d_desc": NM.Desc, "cs3d_stats": NM.Stats, "cs3d_tuning": NM.Tuning}
+    lines = ['#include <stdio.h>', '#include "cs3d.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu %zu\\n", offsetof({cname}, {fname}), '
+                         f"sizeof((({cname}*)0)->{fname}));")
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([gcc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        parts = ln.split()
+        got[(parts[0], parts[1])] = tuple(int(v) for v in parts[2:])
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == (ctypes.sizeof(cls),), cname
+        for fname, _ in cls._fields_:
+            f = getattr(cls, fname)
+            assert got[(cname, fname)] == (f.offset, f.size), (cname, fname, got[(cname, fname)], f.offset, f.size)
+    # every member the header declares is mirrored, in order
+    hdr = open(os.path.join(inc, "cs3d.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", " ", hdr, flags=re.S)
+    hdr = re.sub(r"//[^\n]*", " ", hdr)
+    for cname, cls in structs.items():
+        body = re.search(r"typedef\s+struct\s*\{([^}]*)\}\s*" + cname + r"\s*;", hdr).group(1)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            first, *rest = decl.split(",")
+            names.append(re.sub(r"\[.*?\]", "", first).replace("*", " ").split()[-1])
+            names += [re.sub(r"\[.*?\]", "", r).replace("*", " ").split()[-1] for r in rest]
+        assert names == [f for f, _ in cls._fields_], (cname, names)
