@@ -606,7 +606,11 @@ static hipError_t run_x_fwd_i(const cs3d_plan p, const ProbDev& pd, int nrhs, hi
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fwd_x<T, MX, KIND, TI>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX, KIND, TI>, 64 * kTileJ, lds, ntiles) : ntiles;
+  // workgroups that take the tiles in pairs (the two halves of the lines of G; ldy is a
+  // multiple of 2 kTileJ, so a plane's tiles pair up)
+  static_assert(kTileJ == 8, "tile pairs fill the 16-value rows of the 128-byte lines of G");
+  const int nwork = x_tile_pairs<T, MX>() ? ntiles / 2 : ntiles;
+  const int nb = p->tune.xpersist ? resident_blocks(k_fwd_x<T, MX, KIND, TI>, 64 * kTileJ, lds, nwork) : nwork;
   return launch(k_fwd_x<T, MX, KIND, TI>, dim3(nb), dim3(64 * kTileJ), lds, s, pd, ntiles);
 }
 

@@ -727,6 +727,12 @@ __device__ __forceinline__ XTile decode_xtile(const ProbDev& p, int t, int w) {
   return x;
 }
 
+// K1 workgroups that take the tiles in pairs (see k_fwd_x); the host sizes the grid by it
+template <typename T, int MX>
+__host__ __device__ constexpr bool x_tile_pairs() {
+  return sizeof(T) == 8 && MX >= 512;
+}
+
 // TI: element type of the input p.F (FP32 for the residuals of the mixed path)
 template <typename T, int MX, int KIND = kDst, typename TI = double>
 __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
@@ -748,6 +754,76 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
 #pragma unroll
     for (int k = 0; k < kNV; ++k) pre[k] = (x.active && ln + 64 * k < p.nx) ? Fr[64 * k] : (TI)0;
   };
+  auto fill = [&]() {
+    if (lane == 0) buf[0] = (T)0;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      const int i = 1 + lane + 64 * k;
+      if (i <= p.nx) buf[i] = (T)pre[k];
+    }
+  };
+  if constexpr (x_tile_pairs<T, MX>()) {
+    // FP64 lines of 512 or more points: tiles 2q and 2q + 1 (y-lines jt 8 .. jt 8 + 15 of one
+    // plane, jt even: the rows of G are a multiple of 16 long) fill the two halves of the same
+    // 128-byte lines of G.  One workgroup transforms both, one after the other, and every
+    // thread stores its values of the two back to back, so each line is written whole; with
+    // one tile per workgroup the halves were written apart and 13 % more bytes than the field
+    // reached HBM (K1 at 1023^3 x 4: 19.8-20.3 -> 18.1-18.3 ms).  Shorter lines keep one tile
+    // per workgroup: the second tile's values raise their registers past four waves per SIMD.
+    constexpr int NT = (kMaxLine + kXRows - 1) / kXRows;  // rows per thread for the longest line
+    const int npairs = ntiles / 2;
+    // x-transform of the tile whose rows pre holds, transposed into the LDS tile; thread
+    // (n0, jj) then reads modes n0 + 1, n0 + 65, ... of line jj into v.  `next` is fetched
+    // into pre once the rows are in the line buffers (-1: none).
+    auto tile = [&](int t, int next, T(&v)[NT]) {
+      const XTile x = decode_xtile(p, t, w);
+      __syncthreads();  // every read of the previous tile is done with the LDS
+      settle(pre);
+      fill();
+      if (next >= 0) fetch(next);  // in flight during the transform
+      __syncthreads();              // also publishes the twiddle table on the first pass
+      T out[NS];
+      if (x.active) line_dst<T, MX, 1, false, KIND>(buf, p.nx, out, lane, tab, p.sinx);
+      __syncthreads();
+      if (x.active) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int n = line_mode<MX, 1, KIND>(lane, s, p.nx);
+          if (n > 0) smem[w * ts + n] = out[s];
+        }
+      } else {
+        for (int n = 1 + lane; n <= p.nx; n += 64) smem[w * ts + n] = (T)0;
+      }
+      __syncthreads();
+      const int tid = opaque((int)threadIdx.x);
+      const int n0 = tid / kTileJ, jj = tid % kTileJ;
+      const T* row = smem + jj * ts + n0 + 1;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) v[k] = (n0 + kXRows * k < p.nx) ? row[kXRows * k] : (T)0;
+    };
+    int q = xcd_order(blockIdx.x, gridDim.x);
+    if (q < npairs) fetch(2 * q);
+    for (; q < npairs; q += gridDim.x) {
+      const int qn = q + (int)gridDim.x;
+      T va[NT], vb[NT];
+      tile(2 * q, 2 * q + 1, va);
+      tile(2 * q + 1, qn < npairs ? 2 * qn : -1, vb);
+      const XTile x = decode_xtile(p, 2 * q, w);
+      const int tid = opaque((int)threadIdx.x);
+      const int n0 = tid / kTileJ, jj = tid % kTileJ;
+      T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ +
+             (long long)n0 * p.ldy + jj;
+      const long long step = (long long)kXRows * p.ldy;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (n0 + kXRows * k < p.nx) {
+          G[k * step] = va[k];
+          G[k * step + kTileJ] = vb[k];
+        }
+      }
+    }
+    return;
+  }
   int t = xcd_order(blockIdx.x, gridDim.x);
   if (t < ntiles) fetch(t);
   settle(pre);  // (every path into the loop arrives with settled rows)
@@ -779,9 +855,9 @@ __global__ void __launch_bounds__(64 * kTileJ) k_fwd_x(ProbDev p, int ntiles) {
     settle(pre);  // the next tile's rows, fetched before the transform
     // store phase.  FP64: thread (n0, jj) moves modes n0 + 1, n0 + 65, ... of line jj, all
     // of its LDS reads issued before its stores, so the LDS latency is paid once per tile
-    // rather than once per element (K1 at 1023^3 x 4: 20.6 -> 20.1 ms).  FP32 keeps the
-    // element loop, which measured faster there (39.5 against 43.5 ms for the three
-    // launches of a mixed solve).
+    // rather than once per element (K1 at 1023^3 x 4, one tile per workgroup: 20.6 -> 20.1
+    // ms).  FP32 keeps the element loop, which measured faster there (39.5 against 43.5 ms
+    // for the three launches of a mixed solve).
     if constexpr (sizeof(T) == 4) {
       T* G = reinterpret_cast<T*>(p.G) + x.r * p.G_stride + (long long)(x.l - 1) * p.nx * p.ldy + x.jt * kTileJ;
       for (int idx = threadIdx.x; idx < p.nx * kTileJ; idx += blockDim.x) {
