@@ -246,6 +246,23 @@ def test_plan_tuning_choices(cs3d):
     plan.close()
 
 
+@pytest.mark.parametrize("nx,ny,nz", [(511, 63, 6), (1023, 31, 4)])
+def test_x_pass_tile_pairs_persistent_or_not(cs3d, nx, ny, nz):
+    """x lines of 512 and 1024 points: the forward x pass takes its tiles in pairs (the two
+    halves of the lines of G).  A resident grid walking the pairs and one workgroup per pair
+    give bitwise the same solution, which matches the oracle."""
+    p = WL.noise_problem(nx, ny, nz, "helm4", seed=4100 + nx, boundary=False)
+    plan = cs3d.plan_for_problem(p, device=DEV)
+    f = p.f.to(DEV)
+    plan.set_tuning({"xpersist": 1})
+    base = plan.solve(f).clone()
+    plan.set_tuning({"xpersist": 0})
+    assert torch.equal(plan.solve(f), base)
+    ref = _oracle(p, np.longdouble).U
+    PT.check(f"{p.name} tile pairs", base.cpu().numpy()[0], ref, PT.oracle_bar(_kw(p), ref))
+    plan.close()
+
+
 def test_tuning_cache_roundtrip(cs3d, tmp_path, monkeypatch):
     monkeypatch.setenv("CS3D_TUNE_CACHE", str(tmp_path / "tune.json"))
     monkeypatch.setenv("CS3D_AUTOTUNE", "1")
