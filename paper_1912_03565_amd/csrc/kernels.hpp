@@ -6,8 +6,10 @@
 //               four halo planes in LDS and the thread's own column of five planes in
 //               registers, so f is read from HBM about once; the corrections on the
 //               faces of the box follow in small per-axis passes.
-//  K1 fwd_x   : DST-I along x of 8 x-lines of F per workgroup; the results are
-//               transposed through LDS and stored as y-lines G[l][n][j] (j fastest).
+//  K1 fwd_x   : DST-I along x of 8 x-lines of F per workgroup (two such tiles in turn,
+//               sharing the 128-byte lines of G, for FP64 lines of 512 and 1024 points);
+//               the results are transposed through LDS and stored as y-lines G[l][n][j]
+//               (j fastest).
 //  K2 fwd_y   : one line group (one or two wavefronts) per x-mode n marches l = 1..N_z:
 //               DST-I along y of G[l][n][:], modal eigenvalues lambda^{-,0,+} built on the
 //               fly, forward elimination of the N_y tridiagonal systems (one mode m per
